@@ -1,0 +1,382 @@
+/*
+ * xct_oracle.c -- FP64 CPU oracle for parallel-beam XCT projection,
+ * backprojection and CGLS.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into oracle/liboracle.so
+ * and may be loaded only by the test-suite, by the smoke check and by the
+ * CPU-baseline leg of the benchmark.  The product library never links,
+ * loads or calls it, and it shares no source with the GPU path.
+ *
+ * What it computes (Hidayetoglu et al., "Petascale XCT", SC20):
+ *   - Eq. (1) with R = 0 and no constraint: the least-squares problem
+ *     min ||y - A x||^2, solved by CG on the normal equations (CGLS)
+ *     from x0 = 0 for a fixed iteration count (Sec. II-A, Sec. IV-F and
+ *     the note under Table IV: k iterations = k projections and k+1
+ *     backprojections).
+ *   - A is the Siddon system matrix of a parallel-beam scan (Sec. II-A):
+ *     A[(k,c),(i,j)] = length of the line L_{k,c} inside voxel (i,j).
+ *     Every slice uses the same A (Sec. II-B, "fuse rays along y").
+ *
+ * Geometry readings (the paper fixes none of them):
+ *   - N x N unit voxels centred on the rotation axis; voxel (i,j) is
+ *     [j-N/2, j-N/2+1] x [i-N/2, i-N/2+1]; column index v = i*N + j.
+ *   - theta_k = k*pi/M, k = 0..M-1 (the 0..179 degree example of
+ *     Sec. II-A); normal n_k = (cos, sin), exact at theta = 0 and pi/2.
+ *   - channel offsets t_c = c - (C-1)/2; line L_{k,c} = {p : p.n_k = t_c};
+ *     row index r = k*C + c.
+ *   - a line lying exactly on a voxel edge gives half its length to each
+ *     of the two voxels sharing the edge; lengths below 1e-9 are dropped.
+ *
+ * Three independent ways of getting entries are implemented:
+ *   oracle_siddon_row  -- ray-driven: Siddon's parametric crossing merge
+ *                         (all plane crossings, sorted, one voxel per
+ *                         interval, found from the interval midpoint);
+ *   oracle_voxel_col   -- voxel-driven: for each angle, the channels whose
+ *                         line can meet the voxel, each clipped against the
+ *                         voxel's two slabs (Liang-Barsky);
+ *   brute.py           -- every (ray, voxel) pair by edge intersection.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_DROP 1e-9
+
+static void orc_angle(int M, int k, double *cs, double *sn)
+{
+    if (k == 0) { *cs = 1.0; *sn = 0.0; return; }
+    if (2 * k == M) { *cs = 0.0; *sn = 1.0; return; }
+    double th = M_PI * (double)k / (double)M;
+    *cs = cos(th);
+    *sn = sin(th);
+}
+
+static double orc_offset(int C, int c) { return (double)c - 0.5 * (double)(C - 1); }
+
+static int orc_cmp(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Row r of A by Siddon's method: collect the parameters at which the ray
+ * enters and leaves the grid and crosses every grid plane, sort them, and
+ * give each interval's length to the voxel holding its midpoint.
+ * cols/vals must hold 2N+2 entries.  Returns the entry count. */
+int64_t oracle_siddon_row(int N, int M, int C, int64_t r, int32_t *cols, double *vals)
+{
+    int k = (int)(r / C), c = (int)(r % C);
+    double cs, sn;
+    orc_angle(M, k, &cs, &sn);
+    double t = orc_offset(C, c);
+    double px = t * cs, py = t * sn; /* foot of the perpendicular */
+    double dx = -sn, dy = cs;        /* unit direction */
+    double h = 0.5 * (double)N;
+    double amin = -INFINITY, amax = INFINITY;
+    if (dx != 0.0) {
+        double a1 = (-h - px) / dx, a2 = (h - px) / dx;
+        amin = fmax(amin, fmin(a1, a2));
+        amax = fmin(amax, fmax(a1, a2));
+    } else if (px < -h || px > h) {
+        return 0;
+    }
+    if (dy != 0.0) {
+        double a1 = (-h - py) / dy, a2 = (h - py) / dy;
+        amin = fmax(amin, fmin(a1, a2));
+        amax = fmin(amax, fmax(a1, a2));
+    } else if (py < -h || py > h) {
+        return 0;
+    }
+    if (!(amax - amin > ORC_DROP)) return 0;
+
+    double *al = (double *)malloc(sizeof(double) * (size_t)(2 * N + 6));
+    int na = 0;
+    al[na++] = amin;
+    al[na++] = amax;
+    for (int g = 0; g <= N; ++g) {
+        double plane = (double)g - h;
+        if (dx != 0.0) {
+            double a = (plane - px) / dx;
+            if (a > amin && a < amax) al[na++] = a;
+        }
+        if (dy != 0.0) {
+            double a = (plane - py) / dy;
+            if (a > amin && a < amax) al[na++] = a;
+        }
+    }
+    qsort(al, (size_t)na, sizeof(double), orc_cmp);
+
+    /* a line lying on a grid plane (only possible for theta = 0 or pi/2) */
+    int on_x = (dx == 0.0) && (floor(px + h) == px + h);
+    int on_y = (dy == 0.0) && (floor(py + h) == py + h);
+
+    int64_t n = 0;
+    for (int m = 0; m + 1 < na; ++m) {
+        double len = al[m + 1] - al[m];
+        if (len < ORC_DROP) continue;
+        double am = 0.5 * (al[m] + al[m + 1]);
+        double x = px + am * dx, y = py + am * dy;
+        int j = (int)floor(x + h), i = (int)floor(y + h);
+        if (on_x) {
+            int jb = (int)(px + h); /* the plane x = jb - h */
+            for (int q = jb - 1; q <= jb; ++q) {
+                if (q < 0 || q >= N || i < 0 || i >= N) continue;
+                cols[n] = i * N + q;
+                vals[n] = 0.5 * len;
+                ++n;
+            }
+            continue;
+        }
+        if (on_y) {
+            int ib = (int)(py + h);
+            for (int q = ib - 1; q <= ib; ++q) {
+                if (q < 0 || q >= N || j < 0 || j >= N) continue;
+                cols[n] = q * N + j;
+                vals[n] = 0.5 * len;
+                ++n;
+            }
+            continue;
+        }
+        if (j < 0) j = 0;
+        if (j >= N) j = N - 1;
+        if (i < 0) i = 0;
+        if (i >= N) i = N - 1;
+        cols[n] = i * N + j;
+        vals[n] = len;
+        ++n;
+    }
+    free(al);
+    return n;
+}
+
+/* Length of the line {p : p.(cs,sn) = t} inside [x0,x1] x [y0,y1], by
+ * clipping its parametric form against the two slabs (Liang-Barsky).  A
+ * line lying on an edge of the rectangle counts half. */
+static double orc_clip(double x0, double x1, double y0, double y1, double t, double cs, double sn)
+{
+    double px = t * cs, py = t * sn, dx = -sn, dy = cs;
+    double lo = -INFINITY, hi = INFINITY, w = 1.0;
+    if (dx != 0.0) {
+        double a1 = (x0 - px) / dx, a2 = (x1 - px) / dx;
+        lo = fmax(lo, fmin(a1, a2));
+        hi = fmin(hi, fmax(a1, a2));
+    } else {
+        if (px < x0 || px > x1) return 0.0;
+        if (px == x0 || px == x1) w = 0.5;
+    }
+    if (dy != 0.0) {
+        double a1 = (y0 - py) / dy, a2 = (y1 - py) / dy;
+        lo = fmax(lo, fmin(a1, a2));
+        hi = fmin(hi, fmax(a1, a2));
+    } else {
+        if (py < y0 || py > y1) return 0.0;
+        if (py == y0 || py == y1) w = 0.5;
+    }
+    double len = hi - lo;
+    return len > 0.0 ? w * len : 0.0;
+}
+
+/* Column v of A (row v of A^T), voxel-driven: for every angle, the
+ * channels whose line can reach the voxel (from the corners' projections
+ * onto the normal, widened by one channel each way) are clipped against
+ * the voxel.  rows/vals must hold 4*M entries.  Returns the entry count. */
+int64_t oracle_voxel_col(int N, int M, int C, int64_t v, int32_t *rows, double *vals)
+{
+    int i = (int)(v / N), j = (int)(v % N);
+    double h = 0.5 * (double)N;
+    double x0 = (double)j - h, x1 = x0 + 1.0, y0 = (double)i - h, y1 = y0 + 1.0;
+    int64_t n = 0;
+    for (int k = 0; k < M; ++k) {
+        double cs, sn;
+        orc_angle(M, k, &cs, &sn);
+        double p[4] = {x0 * cs + y0 * sn, x1 * cs + y0 * sn, x0 * cs + y1 * sn, x1 * cs + y1 * sn};
+        double tmin = p[0], tmax = p[0];
+        for (int q = 1; q < 4; ++q) {
+            tmin = fmin(tmin, p[q]);
+            tmax = fmax(tmax, p[q]);
+        }
+        int clo = (int)floor(tmin + 0.5 * (double)(C - 1)) - 1;
+        int chi = (int)ceil(tmax + 0.5 * (double)(C - 1)) + 1;
+        if (clo < 0) clo = 0;
+        if (chi > C - 1) chi = C - 1;
+        for (int c = clo; c <= chi; ++c) {
+            double len = orc_clip(x0, x1, y0, y1, orc_offset(C, c), cs, sn);
+            if (len < ORC_DROP) continue;
+            rows[n] = k * C + c;
+            vals[n] = len;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* ---- explicit CSR forms ------------------------------------------------ */
+
+void oracle_counts_A(int N, int M, int C, int64_t *counts)
+{
+    int64_t R = (int64_t)M * C;
+#pragma omp parallel
+    {
+        int32_t *cb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * N + 2));
+        double *vb = (double *)malloc(sizeof(double) * (size_t)(2 * N + 2));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < R; ++r) counts[r] = oracle_siddon_row(N, M, C, r, cb, vb);
+        free(cb);
+        free(vb);
+    }
+}
+
+void oracle_fill_A(int N, int M, int C, const int64_t *rowptr, int32_t *cols, double *vals)
+{
+    int64_t R = (int64_t)M * C;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < R; ++r) oracle_siddon_row(N, M, C, r, cols + rowptr[r], vals + rowptr[r]);
+}
+
+void oracle_counts_AT(int N, int M, int C, int64_t *counts)
+{
+    int64_t V = (int64_t)N * N;
+#pragma omp parallel
+    {
+        int32_t *rb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * M));
+        double *vb = (double *)malloc(sizeof(double) * (size_t)(4 * M));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t v = 0; v < V; ++v) counts[v] = oracle_voxel_col(N, M, C, v, rb, vb);
+        free(rb);
+        free(vb);
+    }
+}
+
+void oracle_fill_AT(int N, int M, int C, const int64_t *rowptr, int32_t *rows, double *vals)
+{
+    int64_t V = (int64_t)N * N;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t v = 0; v < V; ++v) oracle_voxel_col(N, M, C, v, rows + rowptr[v], vals + rowptr[v]);
+}
+
+/* Y[b][r] = sum_n vals[n] * X[b][cols[n]] over row r, for each of `batch`
+ * slices (Sec. II-B: one matrix shared by every slice). */
+void oracle_csr_spmm(int64_t nrows, const int64_t *rowptr, const int32_t *cols, const double *vals,
+                     int64_t ncols, int batch, const double *x, double *y)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; ++r) {
+        for (int b = 0; b < batch; ++b) {
+            const double *xb = x + (int64_t)b * ncols;
+            double s = 0.0;
+            for (int64_t n = rowptr[r]; n < rowptr[r + 1]; ++n) s += vals[n] * xb[cols[n]];
+            y[(int64_t)b * nrows + r] = s;
+        }
+    }
+}
+
+/* ---- matrix-free forms on sampled rows / voxels ------------------------ */
+
+/* out[b][q] = (A x_b)[rows[q]], tracing each requested ray on the fly. */
+void oracle_project_rows(int N, int M, int C, int batch, const double *x, int64_t nq,
+                         const int64_t *rows, double *out)
+{
+    int64_t V = (int64_t)N * N;
+#pragma omp parallel
+    {
+        int32_t *cb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * N + 2));
+        double *vb = (double *)malloc(sizeof(double) * (size_t)(2 * N + 2));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < nq; ++q) {
+            int64_t n = oracle_siddon_row(N, M, C, rows[q], cb, vb);
+            for (int b = 0; b < batch; ++b) {
+                double s = 0.0;
+                for (int64_t e = 0; e < n; ++e) s += vb[e] * x[(int64_t)b * V + cb[e]];
+                out[(int64_t)b * nq + q] = s;
+            }
+        }
+        free(cb);
+        free(vb);
+    }
+}
+
+/* out[b][q] = (A^T y_b)[vox[q]], from the voxel-driven column. */
+void oracle_backproject_voxels(int N, int M, int C, int batch, const double *y, int64_t nq,
+                               const int64_t *vox, double *out)
+{
+    int64_t R = (int64_t)M * C;
+#pragma omp parallel
+    {
+        int32_t *rb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * M));
+        double *vb = (double *)malloc(sizeof(double) * (size_t)(4 * M));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < nq; ++q) {
+            int64_t n = oracle_voxel_col(N, M, C, vox[q], rb, vb);
+            for (int b = 0; b < batch; ++b) {
+                double s = 0.0;
+                for (int64_t e = 0; e < n; ++e) s += vb[e] * y[(int64_t)b * R + rb[e]];
+                out[(int64_t)b * nq + q] = s;
+            }
+        }
+        free(rb);
+        free(vb);
+    }
+}
+
+/* ---- CGLS ------------------------------------------------------------- */
+
+static double orc_dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t q = 0; q < n; ++q) s += a[q] * b[q];
+    return s;
+}
+
+/* CGLS (CG on A^T A x = A^T y) for each slice independently, from x = 0,
+ * for exactly `iters` iterations: iters products with A and iters+1 with
+ * A^T.  A is (nr x nc) in CSR; At is its transpose in CSR (nc x nr).
+ * resid[k*batch + b] = ||y_b - A x_k|| / ||y_b|| for k = 0..iters (0 when
+ * ||y_b|| = 0).  status[b] = 1 when the slice stopped early because a
+ * step length or direction became zero (gamma = 0 or delta = 0), else 0;
+ * a stopped slice keeps its iterate. */
+void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const double *a_val,
+                 int64_t nc, const int64_t *t_ptr, const int32_t *t_col, const double *t_val,
+                 int batch, const double *y, int iters, double *x, double *resid, int *status)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)nr);
+    double *q = (double *)malloc(sizeof(double) * (size_t)nr);
+    double *s = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *p = (double *)malloc(sizeof(double) * (size_t)nc);
+    for (int b = 0; b < batch; ++b) {
+        const double *yb = y + (int64_t)b * nr;
+        double *xb = x + (int64_t)b * nc;
+        memset(xb, 0, sizeof(double) * (size_t)nc);
+        memcpy(r, yb, sizeof(double) * (size_t)nr);
+        double ynorm = sqrt(orc_dot(nr, yb, yb));
+        oracle_csr_spmm(nc, t_ptr, t_col, t_val, nr, 1, r, s);
+        memcpy(p, s, sizeof(double) * (size_t)nc);
+        double gamma = orc_dot(nc, s, s);
+        int stopped = 0;
+        resid[b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
+        for (int k = 0; k < iters; ++k) {
+            if (!stopped) {
+                oracle_csr_spmm(nr, a_ptr, a_col, a_val, nc, 1, p, q);
+                double delta = orc_dot(nr, q, q);
+                if (gamma == 0.0 || delta == 0.0) {
+                    stopped = 1;
+                } else {
+                    double alpha = gamma / delta;
+                    for (int64_t n = 0; n < nc; ++n) xb[n] += alpha * p[n];
+                    for (int64_t n = 0; n < nr; ++n) r[n] -= alpha * q[n];
+                    oracle_csr_spmm(nc, t_ptr, t_col, t_val, nr, 1, r, s);
+                    double gnew = orc_dot(nc, s, s);
+                    double beta = gnew / gamma;
+                    for (int64_t n = 0; n < nc; ++n) p[n] = s[n] + beta * p[n];
+                    gamma = gnew;
+                }
+            }
+            resid[(int64_t)(k + 1) * batch + b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
+        }
+        status[b] = stopped;
+    }
+    free(r);
+    free(q);
+    free(s);
+    free(p);
+}

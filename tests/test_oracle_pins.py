@@ -1,0 +1,293 @@
+"""Pins for the FP64 CPU oracle: facts fixed by the geometry and by the
+mathematics of least squares, none of them derived from the oracle itself.
+
+Each pin targets a different plausible mistake:
+  * row sums vs the Radon transform of the grid square  -> lost/duplicated
+    segments, wrong entry/exit parameters, wrong detector offsets;
+  * axis-aligned rays                                   -> transposed (i,j),
+    wrong column index v = i*N + j, wrong angle origin;
+  * voxel-aligned rectangles                            -> voxel placement;
+  * the hand-derived 2 x 2 scan                         -> everything at once;
+  * brute force over every (ray, voxel) pair            -> entry-level errors;
+  * ray-driven A vs voxel-driven A^T                    -> either build;
+  * rotations by 90 and 180 degrees                     -> angle sense, channel
+    direction;
+  * disc projections under refinement                   -> lengths vs physics;
+  * CGLS vs Krylov least squares by dense QR, vs lstsq  -> the recurrences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+GEOMS = [(4, 4, 4), (8, 6, 8), (15, 9, 15), (16, 12, 16), (8, 6, 7), (5, 8, 6), (13, 10, 11)]
+
+
+def rect_radon(wx, wy, cx, cy, cs, sn, t):
+    """Chord of the line p.(cs, sn) = t through [cx-wx, cx+wx] x [cy-wy, cy+wy]:
+    the Radon transform of a rectangle, a trapezoid in t (the convolution of the
+    two edge projections).  A line along an edge counts half."""
+    u = np.abs(np.asarray(t, float) - (cx * cs + cy * sn))
+    a, b = abs(cs), abs(sn)
+    if b == 0.0:
+        return np.where(u < wx, 2 * wy, np.where(u == wx, wy, 0.0))
+    if a == 0.0:
+        return np.where(u < wy, 2 * wx, np.where(u == wy, wx, 0.0))
+    p, q = wx * a, wy * b
+    return np.minimum(2 * min(p, q), np.maximum(0.0, p + q - u)) / (a * b)
+
+
+def angles(M):
+    out = []
+    for k in range(M):
+        if k == 0:
+            out.append((1.0, 0.0))
+        elif 2 * k == M:
+            out.append((0.0, 1.0))
+        else:
+            out.append((math.cos(math.pi * k / M), math.sin(math.pi * k / M)))
+    return out
+
+
+@pytest.mark.parametrize("N,M,C", GEOMS + [(64, 30, 64), (33, 17, 40)])
+def test_row_sums_equal_grid_chord(N, M, C):
+    A = oracle.build_A(N, M, C)
+    rs = np.asarray(A.sum(axis=1)).ravel().reshape(M, C)
+    t = np.arange(C) - (C - 1) / 2.0
+    for k, (cs, sn) in enumerate(angles(M)):
+        ref = rect_radon(N / 2, N / 2, 0.0, 0.0, cs, sn, t)
+        np.testing.assert_allclose(rs[k], ref, rtol=0, atol=1e-11 * N)
+
+
+@pytest.mark.parametrize("N", [4, 7, 8, 16])
+def test_axis_aligned_rays(N):
+    M = 6
+    A = oracle.build_A(N, M, N).toarray().reshape(M, N, N, N)  # [k][c][i][j]
+    for c in range(N):
+        ref0 = np.zeros((N, N))
+        ref0[:, c] = 1.0  # theta = 0: the line x = t_c is the centre of column j = c
+        np.testing.assert_array_equal(A[0, c], ref0)
+        ref90 = np.zeros((N, N))
+        ref90[c, :] = 1.0  # theta = pi/2: the line y = t_c is the centre of row i = c
+        np.testing.assert_array_equal(A[M // 2, c], ref90)
+
+
+def test_edge_rule_half_lengths():
+    # N and C of different parity: at theta = 0 every line runs along a
+    # voxel edge and gives half its length to both neighbours.
+    N, C, M = 6, 5, 4
+    A = oracle.build_A(N, M, C).toarray().reshape(M, C, N, N)
+    for c in range(C):
+        x = c - (C - 1) / 2.0  # the line x = t_c lies on the plane j = x + N/2
+        jb = int(x + N / 2)
+        ref = np.zeros((N, N))
+        ref[:, jb - 1] = 0.5
+        ref[:, jb] = 0.5
+        np.testing.assert_array_equal(A[0, c], ref)
+
+
+def test_golden_two_by_two():
+    A = oracle.build_A(2, 4, 2).toarray()
+    ref = np.zeros_like(A)
+    with open(os.path.join(GOLDEN, "siddon_n2_m4_c2.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            r, v, expr = line.split()
+            ref[int(r), int(v)] = {"1": 1.0, "sqrt(2)-1": math.sqrt(2.0) - 1.0}[expr]
+    np.testing.assert_allclose(A, ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("N,M,C", GEOMS)
+def test_brute_force_entrywise(N, M, C):
+    D = brute.dense_A(N, M, C)
+    A = oracle.build_A(N, M, C).toarray()
+    AT = oracle.build_AT(N, M, C).toarray()
+    np.testing.assert_allclose(A, D, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(AT.T, D, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("N,M,C", [(16, 12, 16), (31, 20, 31), (64, 45, 64), (40, 24, 37)])
+def test_adjoint_between_independent_builds(N, M, C):
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((3, N * N))
+    y = rng.standard_normal((3, M * C))
+    Ax = oracle.spmm(A, x)
+    ATy = oracle.spmm(AT, y)
+    for b in range(3):
+        lhs, rhs = Ax[b] @ y[b], x[b] @ ATy[b]
+        assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Ax[b]) * np.linalg.norm(y[b])
+    diff = abs(A - AT.T)
+    assert diff.max() <= 1e-12
+
+
+@pytest.mark.parametrize("N,M", [(16, 12), (17, 8), (32, 20)])
+def test_rotation_symmetries(N, M):
+    C = N
+    A = oracle.build_A(N, M, C)
+    x = np.random.default_rng(2).standard_normal((N, N))
+    p = oracle.project(A, x[None])[0].reshape(M, C)
+    # +90 degrees: x'(p) = x(R^-1 p), x'[i, j] = x[N-1-j, i]
+    x90 = x[::-1, :].T.copy()
+    p90 = oracle.project(A, x90[None])[0].reshape(M, C)
+    h = M // 2
+    np.testing.assert_allclose(p90[h:], p[:M - h], rtol=0, atol=1e-11 * N)
+    np.testing.assert_allclose(p90[:h], p[h:, ::-1], rtol=0, atol=1e-11 * N)
+    # 180 degrees: x'[i, j] = x[N-1-i, N-1-j]  <=>  c -> C-1-c
+    x180 = x[::-1, ::-1].copy()
+    p180 = oracle.project(A, x180[None])[0].reshape(M, C)
+    np.testing.assert_allclose(p180, p[:, ::-1], rtol=0, atol=1e-11 * N)
+
+
+def test_voxel_aligned_rectangle():
+    N, M, C = 24, 16, 24
+    i0, i1, j0, j1, rho = 5, 14, 3, 20, 0.7
+    x = np.zeros((N, N))
+    x[i0:i1, j0:j1] = rho
+    p = oracle.project(oracle.build_A(N, M, C), x[None])[0].reshape(M, C)
+    h = N / 2
+    cx, cy = (j0 + j1) / 2 - h, (i0 + i1) / 2 - h
+    wx, wy = (j1 - j0) / 2, (i1 - i0) / 2
+    t = np.arange(C) - (C - 1) / 2.0
+    for k, (cs, sn) in enumerate(angles(M)):
+        np.testing.assert_allclose(p[k], rho * rect_radon(wx, wy, cx, cy, cs, sn, t),
+                                   rtol=0, atol=1e-12 * N)
+
+
+def _area_disc(N, R, S=16):
+    """Area fraction of each voxel inside the disc |p| <= R (S x S subsamples)."""
+    h = N / 2.0
+    off = (np.arange(S) + 0.5) / S
+    x = np.zeros((N, N))
+    for a in off:
+        for b in off:
+            yy = np.arange(N)[:, None] - h + a
+            xx = np.arange(N)[None, :] - h + b
+            x += (xx * xx + yy * yy) <= R * R
+    return x / (S * S)
+
+
+def test_disc_projection_converges():
+    # R = 0.3 N is a whole number at these N, so the rays grazing the disc sit
+    # at the same place relative to the channel grid at every refinement.
+    errs = []
+    for N in (40, 80, 160):
+        M, C = 12, N
+        R = 0.3 * N
+        x = _area_disc(N, R)
+        p = oracle.project(oracle.build_A(N, M, C), x[None])[0].reshape(M, C)
+        t = np.arange(C) - (C - 1) / 2.0
+        ref = 2.0 * np.sqrt(np.maximum(R * R - t * t, 0.0))
+        errs.append(np.linalg.norm(p - ref[None]) / np.linalg.norm(np.broadcast_to(ref, p.shape)))
+    assert errs[0] < 2e-2
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1], errs  # O(1/N)
+
+
+def test_nnz_model():
+    # nnz ~ f * M * N^2 with f = (2/pi) * int_0^{pi/2} (chord-weighted crossing count)
+    N, M = 128, 180
+    A = oracle.build_A(N, M, N)
+    f = A.nnz / (M * N * N)
+    assert abs(f - 1.1953) < 0.02, f
+
+
+# ---- CGLS -----------------------------------------------------------------
+
+def _krylov_ls(A, y, k):
+    """argmin_{x in K_k(A^T A, A^T y)} ||y - A x|| by an orthonormal Krylov
+    basis (Arnoldi with full reorthogonalisation) and dense least squares."""
+    V = []
+    v = A.T @ y
+    for _ in range(k):
+        for w in V:
+            v = v - (w @ v) * w
+        for w in V:
+            v = v - (w @ v) * w
+        v = v / np.linalg.norm(v)
+        V.append(v)
+        v = A.T @ (A @ v)
+    Vm = np.stack(V, 1)
+    c, *_ = np.linalg.lstsq(A @ Vm, y, rcond=None)
+    return Vm @ c
+
+
+@pytest.mark.parametrize("N,M,C", [(8, 6, 8), (12, 10, 12)])
+def test_cgls_matches_krylov_least_squares(N, M, C):
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    D = brute.dense_A(N, M, C)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((2, M * C))
+    for k in (1, 2, 4, 7, 10):
+        x, res, st = oracle.cgls(A, AT, y, k)
+        for b in range(2):
+            ref = _krylov_ls(D, y[b], k)
+            assert np.linalg.norm(x[b] - ref) <= 1e-8 * np.linalg.norm(ref)
+            r = y[b] - D @ ref
+            assert abs(res[k, b] - np.linalg.norm(r) / np.linalg.norm(y[b])) < 1e-9
+
+
+def test_cgls_reaches_min_norm_least_squares():
+    N, M, C = 4, 6, 4
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    D = brute.dense_A(N, M, C)
+    y = np.random.default_rng(4).standard_normal((1, M * C))
+    # In exact arithmetic CGLS from zero reaches the minimum-norm least-squares
+    # solution in at most n = N*N steps (here A has rank 15 < 16); iterating far
+    # past convergence only amplifies rounding, so stop at n.
+    x, res, st = oracle.cgls(A, AT, y, N * N)
+    ref, *_ = np.linalg.lstsq(D, y[0], rcond=None)
+    assert np.linalg.norm(x[0] - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_cgls_monotone_and_counts():
+    N, M, C = 16, 12, 16
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((3, M * C))
+    xs = []
+    for k in range(0, 12):
+        x, res, st = oracle.cgls(A, AT, y, k)
+        xs.append(np.linalg.norm(x, axis=1))
+    _, res, st = oracle.cgls(A, AT, y, 11)
+    assert np.all(np.diff(res, axis=0) <= 1e-12)
+    assert np.all(np.diff(np.stack(xs), axis=0) >= -1e-12)
+    assert np.all(res[0] == 1.0)
+    assert np.all(st == 0)
+
+
+def test_cgls_zero_sinogram_and_batch_independence():
+    N, M, C = 8, 6, 8
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal((3, M * C))
+    y[1] = 0.0
+    x, res, st = oracle.cgls(A, AT, y, 5)
+    assert np.all(x[1] == 0.0) and np.all(res[:, 1] == 0.0) and st[1] == 1
+    x0, _, _ = oracle.cgls(A, AT, y[[0]], 5)
+    np.testing.assert_array_equal(x0[0], x[0])
+
+
+def test_sampled_rows_and_voxels_match_full_products():
+    N, M, C = 20, 14, 20
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, N * N))
+    y = rng.standard_normal((2, M * C))
+    rows = rng.choice(M * C, 40, replace=False)
+    vox = rng.choice(N * N, 40, replace=False)
+    np.testing.assert_allclose(oracle.project_rows(N, M, C, x, rows), oracle.spmm(A, x)[:, rows],
+                               rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(oracle.backproject_voxels(N, M, C, y, vox), oracle.spmm(AT, y)[:, vox],
+                               rtol=1e-13, atol=1e-13)
