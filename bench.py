@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the XCT hot path on one MI355X.
+
+Workload (the paper-shaped batch the headline metric is quoted on): 16 slices
+of 1024 x 1024 voxels, 1500 angles over [0, pi), 1024 channels, one shared
+Siddon matrix; seeded 40-ellipsoid phantom, synthetic data.
+
+A step is one forward projection y = A x plus one backprojection x = A^T y
+of the whole 16-slice batch through the C ABI (FP32 path: matrix values FP32
+with 16-bit stage-local indices, FP32 vectors), with inputs resident in HBM.
+`value` is the algorithmic bytes of a step per second (GB/s):
+  per product  ceil(B/F) * nnz * b_A  +  B * (n_in + n_out) * 4
+with b_A = 6 (u16 slot + f32 length), n_in/n_out = N^2 and M*C.
+The roofline object covers the SpMM kernel (both operators are launches of
+the same kernel): its algorithmic bytes per launch divided by its launch
+durations, measured with HIP events on the launch stream.
+
+Also reported: CGLS seconds per iteration for the FP32 matrix and for the
+FP16 matrix (16-bit storage of matrix values and kernel operands, FP32
+accumulation), and the FP64 CPU oracle timed on a bounded sample of the same
+products on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "fwd+back projection GB/s & % HBM peak; CGLS s/iter, FP16-store vs FP32"
+
+
+def alg_bytes(nnz, n_in, n_out, B, F, b_a, b_vec=4):
+    return math.ceil(B / F) * nnz * b_a + B * (n_in + n_out) * b_vec
+
+
+def cpu_baseline(N, M, C, B, x_host, bytes_step, budget_s):
+    """FP64 oracle (matrix-free sampled rows of A and voxels of A^T) on the host cores."""
+    import numpy as np
+
+    import oracle
+
+    rng = np.random.default_rng(0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    ys = rng.random((B, M * C))
+
+    def rate(fn, total, n0):
+        idx = rng.choice(total, n0, replace=False)
+        t = time.perf_counter()
+        fn(idx)
+        return n0 / (time.perf_counter() - t)
+
+    fr = lambda idx: oracle.project_rows(N, M, C, x_host, idx)
+    fb = lambda idx: oracle.backproject_voxels(N, M, C, ys, idx)
+    # calibrate, then time a sample sized to about budget_s of CPU work
+    r_rows = rate(fr, M * C, 256)
+    r_vox = rate(fb, N * N, 256)
+    n_rows = int(min(M * C, max(512, r_rows * budget_s / 2)))
+    n_vox = int(min(N * N, max(512, r_vox * budget_s / 2)))
+    r_rows = rate(fr, M * C, n_rows)
+    r_vox = rate(fb, N * N, n_vox)
+    t_full = M * C / r_rows + N * N / r_vox
+    return {
+        "value": bytes_step / t_full / 1e9,
+        "unit": "GB/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle, matrix-free: {n_rows} random rays of A and {n_vox} random voxels of A^T, "
+                   f"each over all {B} slices; full-step time extrapolated linearly "
+                   f"({t_full:.1f} s per fwd+back step)"),
+        "s_per_step": t_full,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cgls-iters", type=int, default=30)
+    ap.add_argument("--no-cgls", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--angles", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=16)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2009_07226_amd as xct
+    from paper_2009_07226_amd import phantoms
+
+    N, M, C, B = args.n, args.angles, args.n, args.batch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"building FP32 matrix N={N} M={M} C={C}")
+    A = xct.Matrix(N, M, C, "f32")
+    info = A.info()
+    log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
+        f"A^T padded {info['AT']['padded']:,}")
+    F = min(16, 1 << max(0, (B - 1).bit_length()))
+    nnz = info["A"]["nnz"]
+    bytes_A = alg_bytes(nnz, N * N, M * C, B, F, 6)
+    bytes_AT = alg_bytes(info["AT"]["nnz"], M * C, N * N, B, F, 6)
+    bytes_step = bytes_A + bytes_AT
+
+    x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device=dev).float()
+    y = torch.empty((B, M, C), dtype=torch.float32, device=dev)
+    xb = torch.empty((B, N, N), dtype=torch.float32, device=dev)
+    ws = A.spmm_workspace(B)
+
+    def step():
+        xct.project(A, x, out=y, workspace=ws)
+        xct.backproject(A, y, out=xb, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    xct.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    xct.profile_enable(False)
+    prof = xct.profile_read()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = bytes_step / (ms_step * 1e-3) / 1e9
+    nA, msA = prof["A"]
+    nT, msT = prof["AT"]
+    kern_bytes_A = nnz * 6 + F * (N * N + M * C) * 4
+    kern_bytes_AT = info["AT"]["nnz"] * 6 + F * (M * C + N * N) * 4
+    launches = nA + nT
+    avg_ms = (msA + msT) / max(launches, 1)
+    achieved = (kern_bytes_A * nA + kern_bytes_AT * nT) / ((msA + msT) * 1e-3) / 1e9
+    log(f"step {ms_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {value:.1f} GB/s; "
+        f"SpMM A {msA / max(nA, 1):.3f} ms, A^T {msT / max(nT, 1):.3f} ms per launch")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{B} slices {N}x{N}, {M} angles over [0,pi), {C} channels, shared Siddon "
+                               f"matrix (FP32 values, 16-bit stage-local indices); 40-ellipsoid phantom",
+                   "n": N, "angles": M, "channels": C, "batch": B, "fuse": F},
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "slice_nnz_per_s": (nnz + info["AT"]["nnz"]) * B / (ms_step * 1e-3),
+        "nnz": nnz,
+        "padded_A": info["A"]["padded"],
+        "padded_AT": info["AT"]["padded"],
+        "build_s_f32": round(info["build_seconds"], 3),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmm<f32,16> (A and A^T launches)",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4),
+            "alg_bytes_per_launch": {"A": kern_bytes_A, "AT": kern_bytes_AT},
+            "launch_ms": {"A": round(msA / max(nA, 1), 4), "AT": round(msT / max(nT, 1), 4)},
+        },
+    }
+
+    if not args.no_cgls:
+        it = args.cgls_iters
+        yc = (y + 0.01 * float(y.abs().max()) * phantoms.noise_torch((M, C), B, 2, dev)).contiguous()
+
+        def cgls_time(Am, iters, reps=2):
+            wsc = Am.cgls_workspace(B, iters)
+            xo = torch.empty((B, N, N), dtype=torch.float32, device=dev)
+            xct.cgls(Am, yc, iters, out=xo, workspace=wsc, want_resid=False)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(reps):
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record()
+                xct.cgls(Am, yc, iters, out=xo, workspace=wsc, want_resid=False)
+                s1.record()
+                torch.cuda.synchronize()
+                best = min(best, s0.elapsed_time(s1) * 1e-3)
+            return best
+
+        log("CGLS FP32")
+        t32 = (cgls_time(A, it) - cgls_time(A, 0)) / it
+        del A
+        torch.cuda.empty_cache()
+        log("building FP16 matrix")
+        A16 = xct.Matrix(N, M, C, "f16")
+        log("CGLS FP16 storage")
+        t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
+        out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),
+                       "fp16_speedup": round(t32 / t16, 3),
+                       "build_s_f16": round(A16.info()["build_seconds"], 3)}
+        log(f"CGLS s/iter FP32 {t32 * 1e3:.3f} ms, FP16 {t16 * 1e3:.3f} ms")
+        del A16
+
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(N, M, C, B, x.double().cpu().numpy().reshape(B, -1), bytes_step,
+                                           args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

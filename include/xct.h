@@ -1,0 +1,206 @@
+/*
+ * xct.h -- C ABI of the MI355X (gfx950) library for parallel-beam XCT:
+ * system-matrix build, forward projection, backprojection and CGLS.
+ *
+ * The operations follow Hidayetoglu et al., "Petascale XCT: 3D Image
+ * Reconstruction with Hierarchical Communications on Multi-GPU Nodes"
+ * (SC20):
+ *   - the least-squares problem of Eq. (1) with R = 0 and no constraint;
+ *   - the parallel-beam Siddon system matrix A (Sec. II-A), memoised once
+ *     and shared by every slice of a batch (Sec. II-B, Sec. III-A.4);
+ *   - projection y = A x and backprojection x = A^T y as sparse
+ *     matrix-times-many-vectors products with staged input buffers, fused
+ *     slices and register accumulators (Sec. III-B, Listing 1);
+ *   - storage of matrix values and kernel operands in 16 bits with FP32
+ *     arithmetic and adaptive max-norm scaling (Sec. III-C);
+ *   - CG on the normal equations (CGLS) from x = 0 for a fixed iteration
+ *     count: k iterations use k projections and k+1 backprojections
+ *     (Sec. IV-F; note under Table IV).
+ *
+ * Geometry (the paper fixes none of it; these are this library's
+ * conventions):
+ *   - a slice is n x n unit voxels centred on the rotation axis; voxel
+ *     (i, j) covers [j - n/2, j - n/2 + 1] x [i - n/2, i - n/2 + 1];
+ *     volumes are stored [batch][n][n] (row i, column j, j fastest);
+ *   - angle k in [0, n_angles) is theta_k = k*pi/n_angles; channel c in
+ *     [0, n_channels) is the line {p : p.(cos theta_k, sin theta_k) =
+ *     c - (n_channels-1)/2}; sinograms are stored
+ *     [batch][n_angles][n_channels] (channel fastest);
+ *   - A[(k, c), (i, j)] is the length of line (k, c) inside voxel (i, j);
+ *     a line lying on a voxel edge gives half its length to each of the
+ *     two voxels; lengths below 1e-9 are dropped.
+ *
+ * Conventions for every call:
+ *   - Pointers named x, y, workspace are DEVICE pointers owned by the
+ *     caller.  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device
+ *     work is enqueued on it; no call synchronises the host except
+ *     xct_build_matrix, xct_matrix_to_coo and xct_cgls (only when it is
+ *     given host result arrays).
+ *   - Functions return XCT_OK or a negative status and never abort; the
+ *     message of the last failure on the calling thread is returned by
+ *     xct_last_error().  Kernel faults surface at the next synchronisation
+ *     as XCT_ERR_HIP.
+ *   - A built matrix is immutable: concurrent calls that share one matrix
+ *     but use separate outputs and workspaces may run on different streams.
+ */
+#ifndef XCT_H
+#define XCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xct_matrix xct_matrix; /* opaque; owns the device copies of A and A^T */
+
+typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2 } xct_dtype;
+
+enum {
+    XCT_OK = 0,
+    XCT_ERR_INVALID = -1,     /* bad argument */
+    XCT_ERR_OOM = -2,         /* device or host allocation failed */
+    XCT_ERR_HIP = -3,         /* a HIP runtime call failed */
+    XCT_ERR_UNSUPPORTED = -4, /* valid request outside what this build supports */
+    XCT_ERR_INTERNAL = -5     /* an internal consistency check failed */
+};
+
+/* Build options; zero in any field selects the default. */
+typedef struct {
+    int tile_waves; /* row tiles (64 rows each, one wavefront) per workgroup; default 8, max 16 */
+    int fuse;       /* largest number of slices fused per matrix pass (F); 1,2,4,8 or 16; default 16 */
+    int lds_bytes;  /* LDS bytes per workgroup for one stage of staged input at F = fuse;
+                       default 81920 (two workgroups per CU) */
+    int xcd_remap;  /* 1 (default): consecutive workgroups of the Hilbert order run on the
+                       same XCD; -1: plain order */
+} xct_build_opts;
+
+/* Statistics of one operator (A or A^T). */
+typedef struct {
+    int64_t nnz;          /* structural nonzeros */
+    int64_t padded;       /* stored entries including ELL padding */
+    int64_t bytes;        /* device bytes of the operator (entries + maps) */
+    int64_t stages;       /* total staging rounds over all workgroups */
+    int64_t staged_slots; /* input slots loaded over all stages (64 per tile) */
+    int32_t blocks;       /* workgroups per pass */
+    int32_t tiles_per_stage;
+} xct_op_stats;
+
+typedef struct {
+    int n, n_angles, n_channels;
+    xct_dtype value_dtype;
+    int fuse;
+    xct_op_stats A;  /* projection operator */
+    xct_op_stats AT; /* backprojection operator */
+    double build_seconds;
+} xct_matrix_info_t;
+
+/*
+ * Build A (rays x voxels) and A^T (voxels x rays) on the GPU
+ * (Sec. II-A, II-B; memoisation as in Sec. II-B "avoids repetitive
+ * computation of A").
+ *   n           slice edge in voxels, 1..8192
+ *   n_angles    angles over [0, pi), >= 1
+ *   n_channels  detector channels, >= 1
+ *   value_dtype storage of matrix values and of the staged kernel operand:
+ *               XCT_F32 (16-bit stage-local index + FP32 value, 6 B per
+ *               entry) or XCT_F16 / XCT_BF16 (index and value packed in
+ *               4 B, Sec. III-C "data packing"); lengths are computed in
+ *               FP64 and rounded to nearest-even once.
+ *   opts        nullable; see xct_build_opts
+ *   stream      stream for the build kernels; the call returns after they finish
+ *   out         receives the handle; release with xct_free_matrix.
+ * Errors: XCT_ERR_INVALID (sizes), XCT_ERR_OOM, XCT_ERR_UNSUPPORTED (a
+ * grid too large for the builder's LDS bitmaps), XCT_ERR_HIP.
+ */
+int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype value_dtype,
+                     const xct_build_opts *opts, void *stream, xct_matrix **out);
+
+/* Release a handle (NULL is ignored).  The caller must make sure no work
+ * that uses it is still queued. */
+void xct_free_matrix(xct_matrix *A);
+
+/* Fill *info (host) with the geometry and per-operator statistics. */
+int xct_matrix_info(const xct_matrix *A, xct_matrix_info_t *info);
+
+/* Device workspace needed by xct_project / xct_backproject for `batch`
+ * slices (staging copies of one fused group of slices in and out). */
+size_t xct_spmm_workspace_bytes(const xct_matrix *A, int batch);
+
+/*
+ * Forward projection y_b = A x_b for b < batch (Sec. III-B; one matrix
+ * pass per group of up to `fuse` slices).
+ *   x         device, [batch][n][n] of dtype `io`
+ *   y         device, [batch][n_angles][n_channels] of dtype `io` (written)
+ *   io        dtype of x and y.  With an F16/BF16 matrix the operand is
+ *             scaled per slice by a power of two no smaller than its
+ *             max-norm before it is rounded to 16 bits, and the FP32 sums
+ *             are scaled back (Sec. III-C "adaptive normalization").
+ *   workspace device, >= xct_spmm_workspace_bytes(A, batch) bytes, 256-B aligned
+ * Inputs must be finite.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ */
+int xct_project(const xct_matrix *A, const void *x, void *y, int batch, xct_dtype io,
+                void *workspace, void *stream);
+
+/* Backprojection x_b = A^T y_b; same conventions as xct_project with the
+ * roles of x and y exchanged (y is read, x is written). */
+int xct_backproject(const xct_matrix *A, const void *y, void *x, int batch, xct_dtype io,
+                    void *workspace, void *stream);
+
+/* Device workspace needed by xct_cgls for `batch` slices and `iters` iterations. */
+size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
+
+/*
+ * CGLS for every slice independently (per-slice step lengths), from
+ * x = 0, for exactly `iters` iterations: iters projections and iters+1
+ * backprojections (Sec. IV-F; Table IV note).
+ *   y          device, [batch][n_angles][n_channels] of dtype `y_dtype`
+ *   x          device, [batch][n][n] FP32 (written)
+ *   iters      >= 0
+ *   workspace  device, >= xct_cgls_workspace_bytes(A, batch, iters) bytes, 256-B aligned
+ *   resid      nullable host, [iters+1][batch]: ||y_b - A x_k|| / ||y_b||
+ *              (0 when y_b = 0)
+ *   status     nullable host, [batch]: 1 when the slice stopped early
+ *              because gamma = ||A^T r||^2 or delta = ||A p||^2 became 0,
+ *              else 0
+ * Solver vectors are FP32 and the per-slice scalars FP64.  With an F16/BF16
+ * matrix the operand of each product is max-norm scaled and rounded to
+ * 16 bits (Sec. III-C).  When resid or status is given the call waits for
+ * the stream before returning.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ */
+int xct_cgls(const xct_matrix *A, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
+             void *workspace, double *resid, int32_t *status, void *stream);
+
+/*
+ * Decode one operator back to coordinate form on the host, in storage
+ * order (for tests and tools).  which = 0: A (row = k*n_channels + c,
+ * col = i*n + j); which = 1: A^T (row = voxel, col = ray).  rows, cols,
+ * vals: host arrays of capacity `cap` entries (>= nnz).  *count receives
+ * the number written.  Also checks the stored layout: every padding entry
+ * must be zero and every slot inside its stage; a violation returns
+ * XCT_ERR_INTERNAL.
+ */
+int xct_matrix_to_coo(const xct_matrix *A, int which, int32_t *rows, int32_t *cols, float *vals,
+                      int64_t cap, int64_t *count);
+
+/*
+ * Kernel timing for measurement tools.  While enabled, every SpMM kernel
+ * launch is bracketed by HIP events recorded on the stream it is launched
+ * on.  xct_profile_read waits for the recorded events and returns, per
+ * operator (index 0: A, 1: A^T), the number of launches and their total
+ * time in milliseconds (host arrays of 2), then clears the record.  Global
+ * to the process and not thread-safe; costs two event records per launch.
+ */
+int xct_profile_enable(int on);
+int xct_profile_read(int64_t *launches, double *ms);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *xct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XCT_H */

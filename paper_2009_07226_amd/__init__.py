@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the projection / backprojection / CGLS
+hot path of parallel-beam XCT reconstruction (Hidayetoglu et al., SC20).
+
+The kernels live in libxct.so (C ABI: include/xct.h); this package is its
+thin binding plus seeded input generators.
+"""
+from .xct import (BF16, F16, F32, Matrix, XctBackproject, XctError, XctProject, backproject, cgls, lib,
+                  library_loaded, profile_enable, profile_read, project)
+
+__all__ = ["Matrix", "project", "backproject", "cgls", "XctProject", "XctBackproject", "XctError", "lib",
+           "library_loaded", "profile_enable", "profile_read", "F32", "F16", "BF16"]

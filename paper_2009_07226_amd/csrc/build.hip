@@ -1,0 +1,721 @@
+// GPU construction of the staged-ELL forms of A and A^T.
+//
+// The paper memoises the Siddon matrix once (Sec. II-B) and reorders both
+// the tomogram and the sinogram by pseudo-Hilbert tiles (Sec. III-A.1,
+// Fig. 3): row tiles in Hilbert order are grouped into thread blocks, and
+// the input footprint of a block is staged through on-chip memory in
+// rounds that each fit the buffer (Sec. III-B "multi-stage 3D buffering";
+// the stage maps of Listing 1).  Here every block builds its own plan:
+//   k_footprint  marks the input tiles its rows touch in an LDS bitmap
+//                indexed by Hilbert rank, and counts them and the entries;
+//   k_plan       writes the touched tiles in Hilbert order (the tile list),
+//                cuts it into stages of T tiles and records, per stage and
+//                wavefront, the longest lane's entry count (the ELL slab);
+//   k_fill       writes every entry at its slab position as a 16-bit
+//                stage-local slot plus the length, rounded to nearest-even
+//                once from FP64 (Sec. III-C "data packing").
+// The three kernels generate the entries of a row with the same code, so
+// they see the same entry set; k_fill still checks every write against the
+// slab bounds and reports a violation instead of writing past it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "geometry.hpp"
+
+namespace xct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// ---- rounding FP64 -> 16-bit, nearest-even, single rounding -------------
+
+__host__ __device__ inline uint16_t dbl_to_half_bits(double v) {
+    // v >= 0 and finite (lengths); scale is bounded by sqrt(2) so no overflow.
+    if (!(v > 0.0)) return 0;
+    union { double d; uint64_t u; } b;
+    b.d = v;
+    int e = (int)((b.u >> 52) & 0x7ff) - 1023;
+    uint64_t m = (b.u & 0xfffffffffffffull) | (1ull << 52);  // 53-bit significand
+    // half: normal exponent range [-14, 15], 10 fraction bits
+    int shift;            // bits of m to drop
+    int ebias;            // biased exponent of the result before rounding carry
+    if (e >= -14) {
+        shift = 52 - 10;
+        ebias = e + 15;
+    } else {
+        shift = 52 - 10 + (-14 - e);
+        ebias = 0;
+        if (shift > 63) return 0;
+    }
+    uint64_t q = m >> shift;
+    uint64_t rem = m & ((1ull << shift) - 1);
+    uint64_t halfway = 1ull << (shift - 1);
+    if (rem > halfway || (rem == halfway && (q & 1))) ++q;
+    if (ebias == 0) return (uint16_t)q;  // subnormal (q may carry into the normal range: still correct)
+    // q has 11 bits (implicit one) unless rounding carried to 12 bits
+    if (q >> 11) { q >>= 1; ++ebias; }
+    if (ebias >= 31) return 0x7c00;
+    return (uint16_t)((ebias << 10) | (q & 0x3ff));
+}
+
+__host__ __device__ inline uint16_t dbl_to_bf16_bits(double v) {
+    if (!(v > 0.0)) return 0;
+    union { double d; uint64_t u; } b;
+    b.d = v;
+    int e = (int)((b.u >> 52) & 0x7ff) - 1023;
+    if (e < -126) return 0;  // below the normal range: not reachable for lengths >= 1e-9
+    uint64_t m = (b.u & 0xfffffffffffffull) | (1ull << 52);
+    const int shift = 52 - 7;
+    uint64_t q = m >> shift;
+    uint64_t rem = m & ((1ull << shift) - 1);
+    uint64_t halfway = 1ull << (shift - 1);
+    if (rem > halfway || (rem == halfway && (q & 1))) ++q;
+    int ebias = e + 127;
+    if (q >> 8) { q >>= 1; ++ebias; }
+    return (uint16_t)((ebias << 7) | (q & 0x7f));
+}
+
+// ---- pseudo-Hilbert ordering of a tile grid ------------------------------
+
+// Distance of (x, y) along the Hilbert curve filling a side x side square
+// (side a power of two): at each scale pick the quadrant, add the cells of
+// the quadrants before it, and rotate/reflect into the quadrant's frame.
+static uint64_t hilbert_index(uint32_t side, uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    for (uint32_t s = side >> 1; s > 0; s >>= 1) {
+        uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = side - 1 - x;
+                y = side - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+// Tiles of a TH x TW grid ordered along the Hilbert curve of the enclosing
+// power-of-two square, skipping cells outside the grid (pseudo-Hilbert).
+static void hilbert_ranks(int TH, int TW, std::vector<int32_t> &rank_of, std::vector<int32_t> &coord_of) {
+    uint32_t side = 1;
+    while (side < (uint32_t)std::max(TH, TW)) side <<= 1;
+    const int64_t n = (int64_t)TH * TW;
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    for (int ty = 0; ty < TH; ++ty)
+        for (int tx = 0; tx < TW; ++tx)
+            key[(int64_t)ty * TW + tx] = {hilbert_index(side, (uint32_t)tx, (uint32_t)ty), ty * TW + tx};
+    std::sort(key.begin(), key.end());
+    rank_of.assign(n, 0);
+    coord_of.assign(n, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        coord_of[r] = key[r].second;
+        rank_of[key[r].second] = (int32_t)r;
+    }
+}
+
+// ---- row generators -------------------------------------------------------
+
+// Rows of A: row tile = sinogram tile (8 angles x 8 channels); inputs are
+// voxel tiles.
+struct ProjRows {
+    int N, M, C;
+    const int32_t *row_coord;  // sinogram rank -> raster tile
+    int rowTW;                 // sinogram tiles per tile row
+    const int32_t *in_rank;    // voxel raster tile -> rank
+    int inTW;
+    template <class V>
+    __device__ __forceinline__ void run(int64_t rt, int lane, V &&v) const {
+        const int coord = row_coord[rt];
+        const int k = (coord / rowTW) * kTile + (lane >> 3);
+        const int c = (coord % rowTW) * kTile + (lane & 7);
+        if (k >= M || c >= C) return;
+        trace_ray(N, M, C, k, c, [&](int i, int j, double len) {
+            v(in_rank[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
+        });
+    }
+};
+
+// Rows of A^T: row tile = voxel tile; inputs are sinogram tiles.
+struct BackRows {
+    int N, M, C;
+    const int32_t *row_coord;  // voxel rank -> raster tile
+    int rowTW;
+    const int32_t *in_rank;    // sinogram raster tile -> rank
+    int inTW;
+    template <class V>
+    __device__ __forceinline__ void run(int64_t rt, int lane, V &&v) const {
+        const int coord = row_coord[rt];
+        const int i = (coord / rowTW) * kTile + (lane >> 3);
+        const int j = (coord % rowTW) * kTile + (lane & 7);
+        if (i >= N || j >= N) return;
+        trace_voxel(N, M, C, i, j, [&](int k, int c, double len) {
+            v(in_rank[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
+        });
+    }
+};
+
+// ---- builder kernels --------------------------------------------------------
+
+struct BuildLds {
+    uint32_t *bits;    // [nwords] touched input tiles, by rank
+    uint32_t *prefix;  // [nwords] set bits before each word
+    int64_t *red;      // [nthr + 1] scratch for reductions / scans
+    uint16_t *cnt;     // [SW][nthr] per-lane entry counters of a stage window
+};
+
+__device__ __forceinline__ BuildLds carve(void *smem, int nwords, int nthr) {
+    BuildLds L;
+    char *p = (char *)smem;
+    L.red = (int64_t *)p;
+    p += sizeof(int64_t) * (size_t)(nthr + 1);
+    L.bits = (uint32_t *)p;
+    p += sizeof(uint32_t) * (size_t)nwords;
+    L.prefix = (uint32_t *)p;
+    p += sizeof(uint32_t) * (size_t)nwords;
+    L.cnt = (uint16_t *)p;
+    return L;
+}
+
+template <class Rows>
+__device__ void mark_tiles(const Rows &rows, int64_t n_row_tiles, const BuildLds &L, int nwords,
+                           int64_t *entries) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int w = tid; w < nwords; w += nthr) L.bits[w] = 0u;
+    __syncthreads();
+    const int W = nthr >> 6;
+    const int64_t rt = (int64_t)blockIdx.x * W + (tid >> 6);
+    int64_t n = 0;
+    if (rt < n_row_tiles) {
+        int last = -1;
+        rows.run(rt, tid & 63, [&](int rank, int, double) {
+            ++n;
+            if (rank == last) return;
+            last = rank;
+            const uint32_t m = 1u << (rank & 31);
+            if (!(L.bits[rank >> 5] & m)) atomicOr(&L.bits[rank >> 5], m);
+        });
+    }
+    if (entries) *entries = n;
+    __syncthreads();
+}
+
+// Sum of one value per thread; result valid in every thread.
+__device__ int64_t block_sum(const BuildLds &L, int64_t v) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    L.red[tid] = v;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t s = 0;
+        for (int t = 0; t < nthr; ++t) s += L.red[t];
+        L.red[nthr] = s;
+    }
+    __syncthreads();
+    const int64_t s = L.red[nthr];
+    __syncthreads();
+    return s;
+}
+
+__device__ void build_prefix(const BuildLds &L, int nwords) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int per = (nwords + nthr - 1) / nthr;
+    const int w0 = min(nwords, tid * per), w1 = min(nwords, w0 + per);
+    int64_t s = 0;
+    for (int w = w0; w < w1; ++w) s += __popc(L.bits[w]);
+    L.red[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int t = 0; t < nthr; ++t) {
+            const int64_t x = L.red[t];
+            L.red[t] = acc;
+            acc += x;
+        }
+        L.red[nthr] = acc;
+    }
+    __syncthreads();
+    uint32_t p = (uint32_t)L.red[tid];
+    for (int w = w0; w < w1; ++w) {
+        L.prefix[w] = p;
+        p += __popc(L.bits[w]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int tile_pos(const BuildLds &L, int rank) {
+    const uint32_t below = (1u << (rank & 31)) - 1u;
+    return (int)(L.prefix[rank >> 5] + __popc(L.bits[rank >> 5] & below));
+}
+
+template <class Rows>
+__global__ void k_footprint(Rows rows, int64_t n_row_tiles, int nwords, int32_t *ntiles, int64_t *nnz) {
+    extern __shared__ __align__(16) char smem[];
+    const BuildLds L = carve(smem, nwords, blockDim.x);
+    int64_t e = 0;
+    mark_tiles(rows, n_row_tiles, L, nwords, &e);
+    int64_t t = 0;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) t += __popc(L.bits[w]);
+    const int64_t tiles = block_sum(L, t);
+    const int64_t ent = block_sum(L, e);
+    if (threadIdx.x == 0) {
+        ntiles[blockIdx.x] = (int32_t)tiles;
+        nnz[blockIdx.x] = ent;
+    }
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <class Rows>
+__global__ void k_plan(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW, const int32_t *blk_tile,
+                       const int32_t *blk_stage, int32_t *tile_list, int32_t *stage_len, int *err) {
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6;
+    const BuildLds L = carve(smem, nwords, nthr);
+    mark_tiles(rows, n_row_tiles, L, nwords, nullptr);
+    build_prefix(L, nwords);
+    const int b = blockIdx.x;
+    const int base = blk_tile[b];
+    const int ntl = blk_tile[b + 1] - base;
+    for (int w = tid; w < nwords; w += nthr) {
+        uint32_t m = L.bits[w];
+        int p = (int)L.prefix[w];
+        while (m) {
+            const int bit = __ffs(m) - 1;
+            if (p >= ntl) {  // footprint differs from the counting pass
+                atomicOr(err, 2);
+                break;
+            }
+            tile_list[base + p++] = w * 32 + bit;
+            m &= m - 1u;
+        }
+    }
+    const int nst = blk_stage[b + 1] - blk_stage[b];
+    const int64_t rt = (int64_t)b * W + wave;
+    for (int s0 = 0; s0 < nst; s0 += SW) {
+        for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
+        __syncthreads();
+        if (rt < n_row_tiles) {
+            rows.run(rt, tid & 63, [&](int rank, int, double) {
+                const int st = tile_pos(L, rank) / T - s0;
+                if (st >= 0 && st < SW && s0 + st < nst) L.cnt[st * nthr + tid] += 1;
+            });
+        }
+        __syncthreads();
+        const int lim = min(SW, nst - s0);
+        for (int st = 0; st < lim; ++st) {
+            const int v = wave_max((int)L.cnt[st * nthr + tid]);
+            if ((tid & 63) == 0)
+                stage_len[(int64_t)(blk_stage[b] + s0 + st) * W + wave] = (v + kGroup - 1) / kGroup;
+        }
+        __syncthreads();
+    }
+}
+
+template <class Rows, int FMT>
+__global__ void k_fill(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW, const int32_t *blk_stage,
+                       const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed, int *err) {
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6, lane = tid & 63;
+    const BuildLds L = carve(smem, nwords, nthr);
+    mark_tiles(rows, n_row_tiles, L, nwords, nullptr);
+    build_prefix(L, nwords);
+    const int b = blockIdx.x;
+    const int nst = blk_stage[b + 1] - blk_stage[b];
+    const int64_t rt = (int64_t)b * W + wave;
+    for (int s0 = 0; s0 < nst; s0 += SW) {
+        for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
+        __syncthreads();
+        if (rt < n_row_tiles) {
+            rows.run(rt, lane, [&](int rank, int off, double len) {
+                const int pos = tile_pos(L, rank);
+                const int st = pos / T;
+                const int sl = st - s0;
+                if (sl < 0 || sl >= SW) return;
+                if (st >= nst) {
+                    atomicOr(err, 4);
+                    return;
+                }
+                const int n = L.cnt[sl * nthr + tid]++;
+                const int64_t gs = (int64_t)(blk_stage[b] + st) * W + wave;
+                const int64_t g = slab[gs] + n / kGroup;
+                if (g >= slab[gs + 1]) {
+                    atomicOr(err, 1);
+                    return;
+                }
+                const int64_t idx = (g * kTileSlots + lane) * kGroup + (n % kGroup);
+                const uint32_t s = (uint32_t)((pos % T) * kTileSlots + off);
+                if (FMT == XCT_F32) {
+                    slot[idx] = (uint16_t)s;
+                    val[idx] = (float)len;
+                } else if (FMT == XCT_F16) {
+                    packed[idx] = (s << 16) | dbl_to_half_bits(len);
+                } else {
+                    packed[idx] = (s << 16) | dbl_to_bf16_bits(len);
+                }
+            });
+        }
+        __syncthreads();
+    }
+}
+
+// ---- host orchestration ---------------------------------------------------
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <class T>
+static int upload(T **dst, const std::vector<T> &src) {
+    XCT_HIP_TRY(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(1, src.size())));
+    if (!src.empty()) XCT_HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return XCT_OK;
+}
+
+static int make_grid(Grid &g, int H, int Wd) {
+    g.H = H;
+    g.Wd = Wd;
+    g.TH = (H + kTile - 1) / kTile;
+    g.TW = (Wd + kTile - 1) / kTile;
+    g.n_tiles = (int64_t)g.TH * g.TW;
+    std::vector<int32_t> rank_of, coord_of;
+    hilbert_ranks(g.TH, g.TW, rank_of, coord_of);
+    int rc = upload(&g.rank_of, rank_of);
+    if (rc) return rc;
+    return upload(&g.coord_of, coord_of);
+}
+
+static void free_op(OpPlan &op) {
+    void *ps[] = {op.blk_stage, op.blk_tile, op.tile_list, op.slab, op.slot, op.val, op.packed};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    op = OpPlan();
+}
+
+template <class Rows>
+static int build_op(OpPlan &op, const Rows &rows, int64_t n_row_tiles, int64_t n_in_tiles, int W, int T,
+                    xct_dtype vdt, hipStream_t st) {
+    op.which = std::is_same<Rows, BackRows>::value ? 1 : 0;
+    op.n_row_tiles = n_row_tiles;
+    op.n_in_tiles = n_in_tiles;
+    op.W = W;
+    op.T = T;
+    op.n_blocks = (int)((n_row_tiles + W - 1) / W);
+    const int nthr = W * kTileSlots;
+    const int nwords = (int)((n_in_tiles + 31) / 32);
+    int dev = 0;
+    XCT_HIP_TRY(hipGetDevice(&dev));
+    int lds_max = 0;
+    XCT_HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t fixed = sizeof(int64_t) * (size_t)(nthr + 1) + sizeof(uint32_t) * 2 * (size_t)nwords;
+    if ((size_t)lds_max < fixed + sizeof(uint16_t) * (size_t)nthr)
+        return fail(XCT_ERR_UNSUPPORTED, "grid too large for the builder's LDS tile bitmap");
+    int SW = (int)std::min<size_t>(64, ((size_t)lds_max - fixed) / (sizeof(uint16_t) * (size_t)nthr));
+    const size_t smem_mark = fixed;
+    const size_t smem_win = fixed + sizeof(uint16_t) * (size_t)SW * nthr;
+
+    const int nb = op.n_blocks;
+    DevBuf d_nt, d_nnz, d_len, d_err;
+    XCT_HIP_TRY(hipMalloc(&d_nt.p, sizeof(int32_t) * nb));
+    XCT_HIP_TRY(hipMalloc(&d_nnz.p, sizeof(int64_t) * nb));
+    XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_footprint<Rows>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_mark));
+    hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, n_row_tiles, nwords,
+                       (int32_t *)d_nt.p, (int64_t *)d_nnz.p);
+    XCT_HIP_TRY(hipGetLastError());
+    std::vector<int32_t> nt(nb);
+    std::vector<int64_t> nnzb(nb);
+    XCT_HIP_TRY(hipMemcpyAsync(nt.data(), d_nt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+    XCT_HIP_TRY(hipMemcpyAsync(nnzb.data(), d_nnz.p, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, st));
+    XCT_HIP_TRY(hipStreamSynchronize(st));
+
+    std::vector<int32_t> blk_tile(nb + 1, 0), blk_stage(nb + 1, 0);
+    int64_t nnz = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t tiles = blk_tile[b] + (int64_t)nt[b];
+        const int64_t stages = blk_stage[b] + (int64_t)(nt[b] + T - 1) / T;
+        if (tiles > INT32_MAX || stages > INT32_MAX) return fail(XCT_ERR_UNSUPPORTED, "tile list too long");
+        blk_tile[b + 1] = (int32_t)tiles;
+        blk_stage[b + 1] = (int32_t)stages;
+        nnz += nnzb[b];
+    }
+    op.n_list = blk_tile[nb];
+    op.n_stages = blk_stage[nb];
+    op.nnz = nnz;
+    op.staged_slots = op.n_list * kTileSlots;
+    int rc = upload(&op.blk_tile, blk_tile);
+    if (!rc) rc = upload(&op.blk_stage, blk_stage);
+    if (rc) return rc;
+    XCT_HIP_TRY(hipMalloc((void **)&op.tile_list, sizeof(int32_t) * std::max<int64_t>(1, op.n_list)));
+    const int64_t nlen = op.n_stages * W;
+    XCT_HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * std::max<int64_t>(1, nlen)));
+    XCT_HIP_TRY(hipMalloc(&d_err.p, sizeof(int)));
+    XCT_HIP_TRY(hipMemsetAsync(d_err.p, 0, sizeof(int), st));
+    XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_plan<Rows>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem_win));
+    hipLaunchKernelGGL(k_plan<Rows>, dim3(nb), dim3(nthr), smem_win, st, rows, n_row_tiles, nwords, T, SW,
+                       op.blk_tile, op.blk_stage, op.tile_list, (int32_t *)d_len.p, (int *)d_err.p);
+    XCT_HIP_TRY(hipGetLastError());
+    std::vector<int32_t> len(nlen);
+    if (nlen) XCT_HIP_TRY(hipMemcpyAsync(len.data(), d_len.p, sizeof(int32_t) * nlen, hipMemcpyDeviceToHost, st));
+    XCT_HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t> slab(nlen + 1, 0);
+    for (int64_t q = 0; q < nlen; ++q) slab[q + 1] = slab[q] + len[q];
+    op.n_groups = slab[nlen];
+    op.padded = op.n_groups * kTileSlots * kGroup;
+    rc = upload(&op.slab, slab);
+    if (rc) return rc;
+    const size_t nent = (size_t)std::max<int64_t>(1, op.padded);
+    if (vdt == XCT_F32) {
+        XCT_HIP_TRY(hipMalloc((void **)&op.slot, sizeof(uint16_t) * nent));
+        XCT_HIP_TRY(hipMalloc((void **)&op.val, sizeof(float) * nent));
+        XCT_HIP_TRY(hipMemsetAsync(op.slot, 0, sizeof(uint16_t) * nent, st));
+        XCT_HIP_TRY(hipMemsetAsync(op.val, 0, sizeof(float) * nent, st));
+    } else {
+        XCT_HIP_TRY(hipMalloc((void **)&op.packed, sizeof(uint32_t) * nent));
+        XCT_HIP_TRY(hipMemsetAsync(op.packed, 0, sizeof(uint32_t) * nent, st));
+    }
+    auto fill = [&](auto kern) -> int {
+        XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)smem_win));
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, n_row_tiles, nwords, T, SW,
+                           op.blk_stage, op.slab, op.slot, op.val, op.packed, (int *)d_err.p);
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    };
+    if (vdt == XCT_F32)
+        rc = fill(k_fill<Rows, XCT_F32>);
+    else if (vdt == XCT_F16)
+        rc = fill(k_fill<Rows, XCT_F16>);
+    else
+        rc = fill(k_fill<Rows, XCT_BF16>);
+    if (rc) return rc;
+    int err = 0;
+    XCT_HIP_TRY(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    XCT_HIP_TRY(hipStreamSynchronize(st));
+    if (err) return fail(XCT_ERR_INTERNAL, "builder passes disagree on the entry set (code " + std::to_string(err) + ")");
+    const int eb = vdt == XCT_F32 ? 6 : 4;
+    op.bytes = op.padded * eb + (int64_t)sizeof(int64_t) * (nlen + 1) + (int64_t)sizeof(int32_t) * op.n_list +
+               (int64_t)sizeof(int32_t) * 2 * (nb + 1);
+    return XCT_OK;
+}
+
+}  // namespace xct
+
+using namespace xct;
+
+extern "C" const char *xct_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void xct_free_matrix(xct_matrix *m) {
+    if (!m) return;
+    free_op(m->A);
+    free_op(m->AT);
+    void *ps[] = {m->vol.rank_of, m->vol.coord_of, m->sino.rank_of, m->sino.coord_of};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype value_dtype,
+                                const xct_build_opts *opts, void *stream, xct_matrix **out) {
+    if (!out) return fail(XCT_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 8192) return fail(XCT_ERR_INVALID, "n must be in [1, 8192]");
+    if (n_angles < 1 || n_angles > 30000) return fail(XCT_ERR_INVALID, "n_angles must be in [1, 30000]");
+    if (n_channels < 1 || n_channels > 16384) return fail(XCT_ERR_INVALID, "n_channels must be in [1, 16384]");
+    if (!valid_dtype(value_dtype)) return fail(XCT_ERR_INVALID, "bad value dtype");
+    xct_build_opts o = {};
+    if (opts) o = *opts;
+    const int W = o.tile_waves ? o.tile_waves : 8;
+    const int F = o.fuse ? o.fuse : 16;
+    int lds = o.lds_bytes;
+    if (W < 1 || W > 16) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16]");
+    if (F != 1 && F != 2 && F != 4 && F != 8 && F != 16) return fail(XCT_ERR_INVALID, "fuse must be 1, 2, 4, 8 or 16");
+    const int per_tile = kTileSlots * F * elem_bytes(value_dtype);
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(XCT_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    int lds_max = 0;
+    he = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (he != hipSuccess) return fail(XCT_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
+    if (!lds) lds = std::min(81920, lds_max);
+    if (lds < per_tile || lds > lds_max) return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
+    int T = lds / per_tile;
+    if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
+    auto t0 = std::chrono::steady_clock::now();
+    xct_matrix *m = new xct_matrix();
+    m->n = n;
+    m->M = n_angles;
+    m->C = n_channels;
+    m->vdt = value_dtype;
+    m->fuse = F;
+    m->remap = o.xcd_remap >= 0 ? 1 : 0;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = make_grid(m->vol, n, n);
+    if (!rc) rc = make_grid(m->sino, n_angles, n_channels);
+    if (!rc) {
+        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.rank_of, m->vol.TW};
+        rc = build_op(m->A, pr, m->sino.n_tiles, m->vol.n_tiles, W, T, value_dtype, st);
+    }
+    if (!rc) {
+        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.rank_of, m->sino.TW};
+        rc = build_op(m->AT, br, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, st);
+    }
+    if (rc) {
+        std::string msg = g_last_error;
+        xct_free_matrix(m);
+        g_last_error = msg;
+        return rc;
+    }
+    m->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = m;
+    return XCT_OK;
+}
+
+static void fill_stats(const OpPlan &op, xct_op_stats &s) {
+    s.nnz = op.nnz;
+    s.padded = op.padded;
+    s.bytes = op.bytes;
+    s.stages = op.n_stages;
+    s.staged_slots = op.staged_slots;
+    s.blocks = op.n_blocks;
+    s.tiles_per_stage = op.T;
+}
+
+extern "C" int xct_matrix_info(const xct_matrix *m, xct_matrix_info_t *info) {
+    if (!m || !info) return fail(XCT_ERR_INVALID, "NULL argument");
+    info->n = m->n;
+    info->n_angles = m->M;
+    info->n_channels = m->C;
+    info->value_dtype = m->vdt;
+    info->fuse = m->fuse;
+    fill_stats(m->A, info->A);
+    fill_stats(m->AT, info->AT);
+    info->build_seconds = m->build_seconds;
+    return XCT_OK;
+}
+
+template <class T>
+static int download(std::vector<T> &dst, const T *src, int64_t n) {
+    dst.resize((size_t)std::max<int64_t>(n, 0));
+    if (n > 0) XCT_HIP_TRY(hipMemcpy(dst.data(), src, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost));
+    return XCT_OK;
+}
+
+static float half_bits_to_float(uint16_t h) {
+    const int e = (h >> 10) & 0x1f, f = h & 0x3ff;
+    float v;
+    if (e == 0)
+        v = std::ldexp((float)f, -24);
+    else if (e == 31)
+        v = f ? NAN : INFINITY;
+    else
+        v = std::ldexp((float)(f | 0x400), e - 25);
+    return (h & 0x8000) ? -v : v;
+}
+
+static float bf16_bits_to_float(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
+extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t *cols, float *vals,
+                                 int64_t cap, int64_t *count) {
+    if (!m || !rows || !cols || !vals || !count) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (which != 0 && which != 1) return fail(XCT_ERR_INVALID, "which must be 0 (A) or 1 (A^T)");
+    const OpPlan &op = which ? m->AT : m->A;
+    const Grid &rg = which ? m->vol : m->sino;
+    const Grid &ig = which ? m->sino : m->vol;
+    std::vector<int32_t> blk_stage, blk_tile, tile_list, rcoord, icoord;
+    std::vector<int64_t> slab;
+    std::vector<uint16_t> slot;
+    std::vector<float> val;
+    std::vector<uint32_t> packed;
+    int rc = download(blk_stage, op.blk_stage, op.n_blocks + 1);
+    if (!rc) rc = download(blk_tile, op.blk_tile, op.n_blocks + 1);
+    if (!rc) rc = download(tile_list, op.tile_list, op.n_list);
+    if (!rc) rc = download(slab, op.slab, op.n_stages * op.W + 1);
+    if (!rc) rc = download(rcoord, rg.coord_of, rg.n_tiles);
+    if (!rc) rc = download(icoord, ig.coord_of, ig.n_tiles);
+    if (!rc && m->vdt == XCT_F32) {
+        rc = download(slot, op.slot, op.padded);
+        if (!rc) rc = download(val, op.val, op.padded);
+    } else if (!rc) {
+        rc = download(packed, op.packed, op.padded);
+    }
+    if (rc) return rc;
+    int64_t n = 0;
+    const int W = op.W, T = op.T;
+    for (int b = 0; b < op.n_blocks; ++b) {
+        for (int s = blk_stage[b]; s < blk_stage[b + 1]; ++s) {
+            const int sl = s - blk_stage[b];
+            const int q0 = blk_tile[b] + sl * T;
+            const int nt = std::min(T, blk_tile[b + 1] - q0);
+            for (int w = 0; w < W; ++w) {
+                const int64_t rt = (int64_t)b * W + w;
+                for (int64_t g = slab[(int64_t)s * W + w]; g < slab[(int64_t)s * W + w + 1]; ++g) {
+                    for (int lane = 0; lane < kTileSlots; ++lane) {
+                        for (int q = 0; q < kGroup; ++q) {
+                            const int64_t idx = (g * kTileSlots + lane) * kGroup + q;
+                            uint32_t sidx;
+                            float v;
+                            if (m->vdt == XCT_F32) {
+                                sidx = slot[idx];
+                                v = val[idx];
+                            } else {
+                                sidx = packed[idx] >> 16;
+                                const uint16_t bits = (uint16_t)(packed[idx] & 0xffff);
+                                v = m->vdt == XCT_F16 ? half_bits_to_float(bits) : bf16_bits_to_float(bits);
+                            }
+                            if (v == 0.0f) {
+                                if (m->vdt == XCT_F32 && sidx != 0)
+                                    return fail(XCT_ERR_INTERNAL, "zero-valued entry with a nonzero slot");
+                                continue;
+                            }
+                            if (rt >= op.n_row_tiles)
+                                return fail(XCT_ERR_INTERNAL, "entry in a padding row tile");
+                            const int pos = (int)(sidx / kTileSlots), off = (int)(sidx % kTileSlots);
+                            if (pos >= nt) return fail(XCT_ERR_INTERNAL, "slot outside its stage");
+                            const int rco = rcoord[rt];
+                            const int r_row = (rco / rg.TW) * kTile + (lane >> 3);
+                            const int r_col = (rco % rg.TW) * kTile + (lane & 7);
+                            const int ico = icoord[tile_list[q0 + pos]];
+                            const int i_row = (ico / ig.TW) * kTile + (off >> 3);
+                            const int i_col = (ico % ig.TW) * kTile + (off & 7);
+                            if (r_row >= rg.H || r_col >= rg.Wd || i_row >= ig.H || i_col >= ig.Wd)
+                                return fail(XCT_ERR_INTERNAL, "entry outside the grid");
+                            if (n >= cap) return fail(XCT_ERR_INVALID, "cap too small");
+                            rows[n] = r_row * rg.Wd + r_col;
+                            cols[n] = i_row * ig.Wd + i_col;
+                            vals[n] = v;
+                            ++n;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    *count = n;
+    return XCT_OK;
+}

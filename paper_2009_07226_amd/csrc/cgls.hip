@@ -1,0 +1,355 @@
+// Device-resident CGLS (CG on A^T A x = A^T y) for a batch of slices.
+//
+// The paper solves Eq. (1) with "CG iterations" whose k-th step costs one
+// projection and one backprojection, plus one backprojection to start
+// (Table IV note: 30 iterations = 30 projections, 31 backprojections), from
+// x = 0 and for a fixed count (Sec. IV-F).  That is CGLS:
+//   r = y, s = A^T r, p = s, gamma = |s|^2
+//   repeat: q = A p, delta = |q|^2, alpha = gamma/delta,
+//           x += alpha p, r -= alpha q, s = A^T r, gamma' = |s|^2,
+//           beta = gamma'/gamma, p = s + beta p, gamma = gamma'.
+// Slices are independent (Sec. II-A), so every slice has its own alpha,
+// beta, gamma and delta.  Vectors stay in the internal tile layout and in
+// FP32 for the whole solve; the scalars are FP64 in device memory and the
+// dot products accumulate in FP64 in a fixed order (bitwise reproducible).
+// |q|^2 and |s|^2 come out of the SpMM epilogue.  With a 16-bit matrix the
+// operand of each product is scaled per slice by a power of two no smaller
+// than its max-norm and rounded to 16 bits, and the FP32 sums are scaled
+// back (Sec. III-C, adaptive normalisation, re-tuned at every product).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace xct {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecBlocks = 1024;
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct CglsWs {
+    int F = 0, n_mb = 0, Bp = 0;
+    int64_t nv = 0, ns = 0;  // elements of one group's volume / sinogram vector
+    float *x = nullptr, *p = nullptr, *s = nullptr, *r = nullptr, *q = nullptr;
+    void *op16 = nullptr;    // one group's 16-bit operand (volume or sinogram sized)
+    double *dotp = nullptr;  // [n_mb][kVecBlocks][F]
+    double *sqp = nullptr;   // [n_mb][max blocks][F]
+    double *gamma = nullptr, *delta = nullptr, *alpha = nullptr, *beta = nullptr, *yy = nullptr, *sum = nullptr;
+    int32_t *stopped = nullptr;
+    double *resid = nullptr;  // [iters+1][Bp]
+    uint32_t *amax = nullptr;
+    float *scale = nullptr, *inv = nullptr;
+    int64_t sq_stride = 0;    // max blocks
+};
+
+static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base, CglsWs *w) {
+    CglsWs c;
+    c.F = run_fuse(batch, m->fuse);
+    c.n_mb = (batch + c.F - 1) / c.F;
+    c.Bp = c.n_mb * c.F;
+    c.nv = m->vol.n_tiles * kTileSlots * c.F;
+    c.ns = m->sino.n_tiles * kTileSlots * c.F;
+    c.sq_stride = std::max(m->A.n_blocks, m->AT.n_blocks);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al256(bytes);
+        return base ? (void *)(base + o) : nullptr;
+    };
+    c.x = (float *)take(sizeof(float) * c.nv * c.n_mb);
+    c.p = (float *)take(sizeof(float) * c.nv * c.n_mb);
+    c.s = (float *)take(sizeof(float) * c.nv * c.n_mb);
+    c.r = (float *)take(sizeof(float) * c.ns * c.n_mb);
+    c.q = (float *)take(sizeof(float) * c.ns * c.n_mb);
+    if (m->vdt != XCT_F32) c.op16 = take(2 * (size_t)std::max(c.nv, c.ns));
+    c.dotp = (double *)take(sizeof(double) * (size_t)c.n_mb * kVecBlocks * c.F);
+    c.sqp = (double *)take(sizeof(double) * (size_t)c.n_mb * c.sq_stride * c.F);
+    c.gamma = (double *)take(sizeof(double) * c.Bp);
+    c.delta = (double *)take(sizeof(double) * c.Bp);
+    c.alpha = (double *)take(sizeof(double) * c.Bp);
+    c.beta = (double *)take(sizeof(double) * c.Bp);
+    c.yy = (double *)take(sizeof(double) * c.Bp);
+    c.sum = (double *)take(sizeof(double) * c.Bp);
+    c.stopped = (int32_t *)take(sizeof(int32_t) * c.Bp);
+    c.resid = (double *)take(sizeof(double) * (size_t)(iters + 1) * c.Bp);
+    c.amax = (uint32_t *)take(sizeof(uint32_t) * 16);
+    c.scale = (float *)take(sizeof(float) * 16);
+    c.inv = (float *)take(sizeof(float) * 16);
+    if (w) *w = c;
+    return off;
+}
+
+// ---- vector kernels (one fused group at a time) -------------------------------
+
+// Block partial sums per slice of v^2 into part[blockIdx.x][F]; the grid
+// stride is a multiple of F so each thread always sees the same slice.
+__device__ __forceinline__ void block_partial(double acc, int F, double *part) {
+    __shared__ double red[kVecThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < F) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < kVecThreads; t += F) s += red[t];
+        part[(int64_t)blockIdx.x * F + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_sqnorm(const float *v, int64_t n, int F, double *part) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = v[i];
+        acc += t * t;
+    }
+    block_partial(acc, F, part);
+}
+
+// x += alpha p ; (volume)
+__global__ void k_axpy_vol(float *x, const float *p, int64_t n, int F, const double *alpha) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float a = (float)alpha[i & (F - 1)];
+        x[i] = fmaf(a, p[i], x[i]);
+    }
+}
+
+// r -= alpha q, with block partials of |r|^2 (sinogram)
+__global__ void k_axpy_res(float *r, const float *q, int64_t n, int F, const double *alpha, double *part) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float a = (float)alpha[i & (F - 1)];
+        const float t = fmaf(-a, q[i], r[i]);
+        r[i] = t;
+        acc += (double)t * (double)t;
+    }
+    block_partial(acc, F, part);
+}
+
+// p = s + beta p
+__global__ void k_xpby(float *p, const float *s, int64_t n, int F, const double *beta) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float bt = (float)beta[i & (F - 1)];
+        p[i] = fmaf(bt, p[i], s[i]);
+    }
+}
+
+// Per-slice max |v| of an internal-layout group vector.
+__global__ void k_absmax_int(const float *v, int64_t n, int F, uint32_t *amax) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(v[i]));
+    __shared__ float red[kVecThreads];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    if ((int)threadIdx.x < F) {
+        for (int t = threadIdx.x + F; t < kVecThreads; t += F) m = fmaxf(m, red[t]);
+        atomicMax(&amax[threadIdx.x], __float_as_uint(m));
+    }
+}
+
+__device__ __forceinline__ uint32_t to16(float v, int fmt) {
+    if (fmt == XCT_F16) return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+    uint32_t u = __builtin_bit_cast(uint32_t, v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// o16 = round16(v * inv[slice])
+__global__ void k_cast16(const float *v, int64_t n, int F, const float *inv, uint16_t *o16, int fmt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        o16[i] = (uint16_t)to16(v[i] * inv[i & (F - 1)], fmt);
+}
+
+// ---- per-slice scalar updates --------------------------------------------------
+
+// sum[b] = sum over blocks of part[m][blk][f], b = m*F + f, fixed order.
+__global__ void k_reduce(const double *part, int64_t stride, int nblk, int F, int Bp, double *sum) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bp) return;
+    const int m = b / F, f = b % F;
+    const double *p = part + (int64_t)m * stride * F;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += p[(int64_t)k * F + f];
+    sum[b] = s;
+}
+
+enum { kSetGamma = 0, kSetAlpha = 1, kSetBeta = 2, kSetYY = 3, kSetResid = 4 };
+
+__global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, double *delta, double *alpha,
+                          double *beta, double *yy, int32_t *stopped, double *resid_row) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bp) return;
+    const double v = sum[b];
+    switch (mode) {
+        case kSetYY:
+            yy[b] = v;
+            stopped[b] = 0;
+            resid_row[b] = v > 0.0 ? 1.0 : 0.0;
+            break;
+        case kSetGamma:
+            gamma[b] = v;
+            break;
+        case kSetAlpha: {
+            delta[b] = v;
+            const double g = gamma[b];
+            if (stopped[b] || g == 0.0 || v == 0.0) {
+                stopped[b] = 1;
+                alpha[b] = 0.0;
+            } else {
+                alpha[b] = g / v;
+            }
+            break;
+        }
+        case kSetResid:
+            resid_row[b] = yy[b] > 0.0 ? sqrt(v / yy[b]) : 0.0;
+            break;
+        case kSetBeta:
+            if (stopped[b]) {
+                beta[b] = 0.0;
+            } else {
+                beta[b] = v / gamma[b];
+                gamma[b] = v;
+            }
+            break;
+    }
+}
+
+// ---- orchestration -----------------------------------------------------------
+
+struct Cgls {
+    const xct_matrix *m;
+    CglsWs w;
+    hipStream_t st;
+    int grid_v, grid_s;
+
+    int vec_grid(int64_t n) const {
+        return (int)std::max<int64_t>(1, std::min<int64_t>(kVecBlocks, (n + kVecThreads - 1) / kVecThreads));
+    }
+
+    int scalars(int mode, double *resid_row) {
+        hipLaunchKernelGGL(k_scalars, dim3((w.Bp + 255) / 256), dim3(256), 0, st, mode, w.Bp, (const double *)w.sum,
+                           w.gamma, w.delta, w.alpha, w.beta, w.yy, w.stopped, resid_row);
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
+
+    int reduce(const double *part, int64_t stride, int nblk) {
+        hipLaunchKernelGGL(k_reduce, dim3((w.Bp + 255) / 256), dim3(256), 0, st, part, stride, nblk, w.F, w.Bp, w.sum);
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
+
+    // One product (dir 0: q = A p, dir 1: s = A^T r) for every group, with
+    // the per-block squared-output partials, then their per-slice sums.
+    int product(int dir) {
+        const OpPlan &op = dir ? m->AT : m->A;
+        const int64_t nin = dir ? w.ns : w.nv, nout = dir ? w.nv : w.ns;
+        float *in = dir ? w.r : w.p;
+        float *out = dir ? w.s : w.q;
+        for (int g = 0; g < w.n_mb; ++g) {
+            float *gin = in + (int64_t)g * nin;
+            const void *opnd = gin;
+            const float *scale = nullptr;
+            if (m->vdt != XCT_F32) {
+                const int gg = vec_grid(nin);
+                hipLaunchKernelGGL(k_absmax_int, dim3(gg), dim3(kVecThreads), 0, st, (const float *)gin, nin, w.F, w.amax);
+                XCT_HIP_TRY(hipGetLastError());
+                int rc0 = launch_pow2_scale(w.amax, w.F, w.scale, w.inv, st);
+                if (rc0) return rc0;
+                hipLaunchKernelGGL(k_cast16, dim3(gg), dim3(kVecThreads), 0, st, (const float *)gin, nin, w.F,
+                                   (const float *)w.inv, (uint16_t *)w.op16, (int)m->vdt);
+                XCT_HIP_TRY(hipGetLastError());
+                opnd = w.op16;
+                scale = w.scale;
+            }
+            SpmmLaunch L{&op, opnd, out + (int64_t)g * nout, scale, w.sqp + (int64_t)g * w.sq_stride * w.F, w.F,
+                         m->vdt, m->remap};
+            int rc = launch_spmm(L, st);
+            if (rc) return rc;
+        }
+        return reduce(w.sqp, w.sq_stride, op.n_blocks);
+    }
+};
+
+}  // namespace xct
+
+using namespace xct;
+
+extern "C" size_t xct_cgls_workspace_bytes(const xct_matrix *m, int batch, int iters) {
+    if (!m || batch < 1 || iters < 0) return 0;
+    return cgls_layout(m, batch, iters, nullptr, nullptr);
+}
+
+extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
+                        void *workspace, double *resid, int32_t *status, void *stream) {
+    if (!m || !y || !x || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (batch < 1 || iters < 0) return fail(XCT_ERR_INVALID, "batch must be >= 1 and iters >= 0");
+    if (!valid_dtype(y_dtype)) return fail(XCT_ERR_INVALID, "bad y dtype");
+    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
+    Cgls c;
+    c.m = m;
+    c.st = (hipStream_t)stream;
+    cgls_layout(m, batch, iters, (char *)workspace, &c.w);
+    CglsWs &w = c.w;
+    hipStream_t st = c.st;
+    const int gv = c.vec_grid(w.nv), gs = c.vec_grid(w.ns);
+    int rc;
+    XCT_HIP_TRY(hipMemsetAsync(w.amax, 0, sizeof(uint32_t) * 16, st));
+    // r = y ; x = 0 ; yy = |y|^2
+    for (int g = 0; g < w.n_mb; ++g) {
+        rc = launch_to_internal(m->sino, y, y_dtype, batch, g * w.F, w.F, w.r + (int64_t)g * w.ns, XCT_F32, nullptr, st);
+        if (rc) return rc;
+    }
+    XCT_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(float) * w.nv * w.n_mb, st));
+    for (int g = 0; g < w.n_mb; ++g) {
+        hipLaunchKernelGGL(k_sqnorm, dim3(gs), dim3(kVecThreads), 0, st, (const float *)(w.r + (int64_t)g * w.ns), w.ns,
+                           w.F, w.dotp + (int64_t)g * kVecBlocks * w.F);
+    }
+    XCT_HIP_TRY(hipGetLastError());
+    if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
+    if ((rc = c.scalars(kSetYY, w.resid))) return rc;
+    // s = A^T r ; gamma = |s|^2 ; p = s
+    if ((rc = c.product(1))) return rc;
+    if ((rc = c.scalars(kSetGamma, nullptr))) return rc;
+    XCT_HIP_TRY(hipMemcpyAsync(w.p, w.s, sizeof(float) * w.nv * w.n_mb, hipMemcpyDeviceToDevice, st));
+    for (int k = 0; k < iters; ++k) {
+        if ((rc = c.product(0))) return rc;  // q = A p, delta
+        if ((rc = c.scalars(kSetAlpha, nullptr))) return rc;
+        for (int g = 0; g < w.n_mb; ++g) {
+            hipLaunchKernelGGL(k_axpy_vol, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
+                               (const float *)(w.p + (int64_t)g * w.nv), w.nv, w.F, (const double *)(w.alpha + g * w.F));
+            hipLaunchKernelGGL(k_axpy_res, dim3(gs), dim3(kVecThreads), 0, st, w.r + (int64_t)g * w.ns,
+                               (const float *)(w.q + (int64_t)g * w.ns), w.ns, w.F, (const double *)(w.alpha + g * w.F),
+                               w.dotp + (int64_t)g * kVecBlocks * w.F);
+        }
+        XCT_HIP_TRY(hipGetLastError());
+        if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
+        if ((rc = c.scalars(kSetResid, w.resid + (int64_t)(k + 1) * w.Bp))) return rc;
+        if ((rc = c.product(1))) return rc;  // s = A^T r, gamma'
+        if ((rc = c.scalars(kSetBeta, nullptr))) return rc;
+        for (int g = 0; g < w.n_mb; ++g) {
+            hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(kVecThreads), 0, st, w.p + (int64_t)g * w.nv,
+                               (const float *)(w.s + (int64_t)g * w.nv), w.nv, w.F, (const double *)(w.beta + g * w.F));
+        }
+        XCT_HIP_TRY(hipGetLastError());
+    }
+    for (int g = 0; g < w.n_mb; ++g) {
+        rc = launch_from_internal(m->vol, w.x + (int64_t)g * w.nv, batch, g * w.F, w.F, x, XCT_F32, st);
+        if (rc) return rc;
+    }
+    if (resid || status) {
+        std::vector<double> rh((size_t)(iters + 1) * w.Bp);
+        std::vector<int32_t> sh(w.Bp);
+        XCT_HIP_TRY(hipMemcpyAsync(rh.data(), w.resid, sizeof(double) * rh.size(), hipMemcpyDeviceToHost, st));
+        XCT_HIP_TRY(hipMemcpyAsync(sh.data(), w.stopped, sizeof(int32_t) * sh.size(), hipMemcpyDeviceToHost, st));
+        XCT_HIP_TRY(hipStreamSynchronize(st));
+        if (resid)
+            for (int k = 0; k <= iters; ++k)
+                for (int b = 0; b < batch; ++b) resid[(int64_t)k * batch + b] = rh[(size_t)k * w.Bp + b];
+        if (status)
+            for (int b = 0; b < batch; ++b) status[b] = sh[b];
+    }
+    return XCT_OK;
+}

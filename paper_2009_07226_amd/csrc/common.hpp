@@ -1,0 +1,129 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/xct.h"
+
+namespace xct {
+
+// A tile is 8 x 8 elements of a 2D grid (voxels of a slice, or angles x
+// channels of a sinogram): 64 slots, one wavefront of rows.
+constexpr int kTile = 8;
+constexpr int kTileSlots = 64;
+// ELL entries are stored in groups of kGroup consecutive steps per lane so
+// one lane reads a group with a single wide load.
+constexpr int kGroup = 4;
+
+// One operator (A or A^T) in staged-ELL form.
+//
+// Output rows are grouped in tiles of 64 (one wavefront); W consecutive row
+// tiles in Hilbert order make one workgroup ("block").  The input tiles a
+// block touches, in Hilbert order, form its tile list; the list is cut into
+// stages of at most T tiles, each loaded into LDS in turn.  For stage s and
+// wave w the entries of the wave's 64 rows that fall in the stage form one
+// ELL slab of slab[s*W+w+1]-slab[s*W+w] groups; entry (group g, lane l,
+// step q) lives at index (g*64 + l)*kGroup + q and holds the stage-local
+// slot (tile position in stage * 64 + offset in tile) and the length.
+struct OpPlan {
+    int which = 0;  // 0: A (projection), 1: A^T (backprojection)
+    int64_t n_row_tiles = 0;
+    int64_t n_in_tiles = 0;
+    int W = 0;  // row tiles (wavefronts) per block
+    int T = 0;  // input tiles per stage
+    int n_blocks = 0;
+    int64_t n_stages = 0;
+    int64_t n_groups = 0;
+    int64_t n_list = 0;
+    int32_t *blk_stage = nullptr;  // [n_blocks+1]
+    int32_t *blk_tile = nullptr;   // [n_blocks+1]
+    int32_t *tile_list = nullptr;  // [n_list] input tile ranks
+    int64_t *slab = nullptr;       // [n_stages*W+1] group offsets
+    uint16_t *slot = nullptr;      // F32 format, [n_groups*64*kGroup]
+    float *val = nullptr;          // F32 format, [n_groups*64*kGroup]
+    uint32_t *packed = nullptr;    // F16/BF16 format: slot << 16 | value bits
+    int64_t nnz = 0, padded = 0, staged_slots = 0, bytes = 0;
+};
+
+// Geometry of one tiled 2D grid (H rows x Wd columns).
+struct Grid {
+    int H = 0, Wd = 0;
+    int TH = 0, TW = 0;            // tiles per column / per row
+    int64_t n_tiles = 0;
+    int32_t *rank_of = nullptr;    // [TH*TW] raster tile -> Hilbert rank (device)
+    int32_t *coord_of = nullptr;   // [n_tiles] Hilbert rank -> raster tile (device)
+};
+
+}  // namespace xct
+
+struct xct_matrix {
+    int n = 0, M = 0, C = 0;
+    xct_dtype vdt = XCT_F32;
+    int fuse = 16;
+    int remap = 1;
+    xct::Grid vol, sino;
+    xct::OpPlan A, AT;
+    double build_seconds = 0.0;
+};
+
+namespace xct {
+
+// thread-local last error
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define XCT_HIP_TRY(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::xct::fail(e_ == hipErrorOutOfMemory ? XCT_ERR_OOM : XCT_ERR_HIP,       \
+                               std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+inline int elem_bytes(xct_dtype d) { return d == XCT_F32 ? 4 : 2; }
+inline bool valid_dtype(int d) { return d == XCT_F32 || d == XCT_F16 || d == XCT_BF16; }
+
+// Fused slice count used for a batch: the smallest supported F >= min(batch, fuse).
+inline int run_fuse(int batch, int fuse) {
+    int want = batch < fuse ? batch : fuse;
+    int f = 1;
+    while (f < want) f <<= 1;
+    return f;
+}
+
+// Launch of one staged SpMM pass over a single fused group of F slices.
+struct SpmmLaunch {
+    const OpPlan *op;
+    const void *xin;      // internal layout [in tiles][64][F], storage dtype
+    float *yout;          // internal layout [row tiles][64][F], FP32
+    const float *scale;   // [F] per-slice output scale or nullptr
+    double *sq_partial;   // [n_blocks][F] per-block sums of squared outputs or nullptr
+    int F;
+    xct_dtype vdt;
+    int remap;
+};
+int launch_spmm(const SpmmLaunch &L, hipStream_t s);
+
+// Natural <-> internal layout conversion for one fused group.
+//   natural: [batch][H][Wd] of dtype io; group covers slices s0 .. s0+F-1
+//   internal: [n_tiles][64][F]
+//   to_internal: optional per-slice inverse scale (1/m) read from device
+//   memory `inv_scale` [F]; values for slices >= batch are zero.
+int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F,
+                       void *internal, xct_dtype storage, const float *inv_scale, hipStream_t s);
+int launch_from_internal(const Grid &g, const float *internal, int batch, int s0, int F, void *nat,
+                         xct_dtype io, hipStream_t s);
+// From per-slice max |v| bits in amax[F]: scale[f] = m = 2^ceil(log2 max)
+// (1 for zero), inv[f] = 1/m; clears amax for reuse.
+int launch_pow2_scale(uint32_t *amax, int F, float *scale, float *inv, hipStream_t s);
+// Per-slice max |v| of a natural-layout group, accumulated as float bits into
+// amax[F] (zero on entry), then launch_pow2_scale.
+int launch_natural_scale(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F,
+                         uint32_t *amax, float *scale, float *inv, hipStream_t s);
+
+}  // namespace xct

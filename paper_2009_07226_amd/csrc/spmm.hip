@@ -1,0 +1,544 @@
+// Staged sparse-matrix times fused-slices product (projection with A,
+// backprojection with A^T), and the layout conversions around it.
+//
+// The paper's XCT-optimised SpMM (Sec. III-B, Listing 1): one thread per
+// output row holds the partial sums of F fused slices in registers
+// ("3D output buffering"); each (index, length) pair is read once and used
+// for all F slices ("register reuse"); the input footprint of a block is
+// staged through on-chip memory stage by stage ("3D input buffering",
+// "multi-stage"), indices being stage-local.  The same kernel serves A and
+// A^T.  16-bit storage with FP32 arithmetic follows Sec. III-C.
+//
+// gfx950 design:
+//   * a row tile of 64 rows is exactly one wave64; a workgroup is W row
+//     tiles, consecutive along the Hilbert curve;
+//   * vectors live in a tile-interleaved layout [tile][64][F] so a stage
+//     load copies whole 64*F-element tiles (contiguous, 16 B per lane) and a
+//     lane's F operands of one slot are one contiguous LDS row, read with
+//     16-byte LDS loads;
+//   * ELL entries are grouped four steps per lane so one lane fetches four
+//     (slot, length) pairs with one wide non-temporal load (the matrix is
+//     streamed once per pass and should not evict the vectors from L2/MALL);
+//   * workgroup ids are remapped so that consecutive blocks of the Hilbert
+//     order (which share most of their input footprint) run on one XCD and
+//     share its L2.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+namespace xct {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float h16_to_f32(uint32_t bits) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
+
+// Storage element of the staged operand.
+template <int FMT> struct Stor;
+template <> struct Stor<XCT_F32> { typedef float T; };
+template <> struct Stor<XCT_F16> { typedef uint16_t T; };
+template <> struct Stor<XCT_BF16> { typedef uint16_t T; };
+
+// Read the F operands of one LDS row as FP32.
+template <int FMT, int F>
+__device__ __forceinline__ void lds_row(const typename Stor<FMT>::T *row, float (&x)[F]) {
+    if constexpr (FMT == XCT_F32) {
+        if constexpr (F >= 4) {
+#pragma unroll
+            for (int q = 0; q < F / 4; ++q) {
+                const f32x4 v = ((const f32x4 *)row)[q];
+                x[4 * q + 0] = v.x;
+                x[4 * q + 1] = v.y;
+                x[4 * q + 2] = v.z;
+                x[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) x[f] = row[f];
+        }
+    } else {
+        constexpr int words = (F + 1) / 2;  // 32-bit words holding F 16-bit values
+        uint32_t w[words];
+        if constexpr (words >= 4) {
+#pragma unroll
+            for (int q = 0; q < words / 4; ++q) {
+                const u32x4 v = ((const u32x4 *)row)[q];
+                w[4 * q + 0] = v.x;
+                w[4 * q + 1] = v.y;
+                w[4 * q + 2] = v.z;
+                w[4 * q + 3] = v.w;
+            }
+        } else if constexpr (words == 2) {
+            const u32x2 v = *(const u32x2 *)row;
+            w[0] = v.x;
+            w[1] = v.y;
+        } else if constexpr (F == 2) {
+            w[0] = *(const uint32_t *)row;
+        } else {
+            w[0] = *(const uint16_t *)row;
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const uint32_t b = (f & 1) ? (w[f >> 1] >> 16) : (w[f >> 1] & 0xffffu);
+            x[f] = FMT == XCT_F16 ? h16_to_f32(b) : bf16_to_f32(b);
+        }
+    }
+}
+
+struct SpmmArgs {
+    const int32_t *blk_stage, *blk_tile, *tile_list;
+    const int64_t *slab;
+    const uint16_t *slot;
+    const float *val;
+    const uint32_t *packed;
+    const void *xin;
+    float *yout;
+    const float *scale;
+    double *sq_partial;
+    int64_t n_row_tiles;
+    int n_blocks, T, remap;
+};
+
+template <int FMT, int F>
+__global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
+    typedef typename Stor<FMT>::T XT;
+    extern __shared__ __align__(16) char smem[];
+    XT *lds = (XT *)smem;
+    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6;
+    const int wave = tid >> 6, lane = tid & 63;
+    int b = blockIdx.x;
+    if (a.remap) {
+        const int per = (a.n_blocks + 7) >> 3;
+        b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    }
+    if (b >= a.n_blocks) return;  // whole workgroup, before any barrier
+
+    float acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = 0.f;
+
+    constexpr int kVecPerTile = kTileSlots * F * (int)sizeof(XT) / 16;  // 16-byte chunks per tile
+    const int s0 = a.blk_stage[b], s1 = a.blk_stage[b + 1];
+    const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
+    const u32x4 *xin = (const u32x4 *)a.xin;
+    u32x4 *ldsv = (u32x4 *)smem;
+    for (int s = s0; s < s1; ++s) {
+        const int q0 = t0 + (s - s0) * a.T;
+        const int nt = min(a.T, t1 - q0);
+        __syncthreads();  // previous stage fully consumed
+        for (int e = tid; e < nt * kVecPerTile; e += nthr) {
+            const int q = e / kVecPerTile, r = e % kVecPerTile;
+            const int tile = a.tile_list[q0 + q];
+            ldsv[e] = xin[(int64_t)tile * kVecPerTile + r];
+        }
+        __syncthreads();
+        const int64_t g0 = a.slab[(int64_t)s * W + wave], g1 = a.slab[(int64_t)s * W + wave + 1];
+        for (int64_t g = g0; g < g1; ++g) {
+            const int64_t e = g * kTileSlots + lane;
+            uint32_t sl[kGroup];
+            float v[kGroup];
+            if constexpr (FMT == XCT_F32) {
+                const u32x2 s2 = __builtin_nontemporal_load((const u32x2 *)a.slot + e);
+                const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)a.val + e);
+                sl[0] = s2.x & 0xffffu;
+                sl[1] = s2.x >> 16;
+                sl[2] = s2.y & 0xffffu;
+                sl[3] = s2.y >> 16;
+                v[0] = v4.x;
+                v[1] = v4.y;
+                v[2] = v4.z;
+                v[3] = v4.w;
+            } else {
+                const u32x4 p4 = __builtin_nontemporal_load((const u32x4 *)a.packed + e);
+                const uint32_t p[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    sl[q] = p[q] >> 16;
+                    v[q] = FMT == XCT_F16 ? h16_to_f32(p[q] & 0xffffu) : bf16_to_f32(p[q] & 0xffffu);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                float x[F];
+                lds_row<FMT, F>(lds + (int)sl[q] * F, x);
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[f] = fmaf(v[q], x[f], acc[f]);
+            }
+        }
+    }
+
+    const int64_t rt = (int64_t)b * W + wave;
+    if (a.scale) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] *= a.scale[f];
+    }
+    if (rt < a.n_row_tiles) {
+        float *out = a.yout + (rt * kTileSlots + lane) * F;
+        if constexpr (F >= 4) {
+#pragma unroll
+            for (int q = 0; q < F / 4; ++q)
+                ((f32x4 *)out)[q] = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[f] = acc[f];
+        }
+    }
+    if (a.sq_partial) {
+        // per-slice sum of squares of this block's outputs, in FP64, fixed order
+        __syncthreads();
+        double *red = (double *)smem;  // [W][F]
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            double q = (double)acc[f] * (double)acc[f];
+            for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+            if (lane == 0) red[wave * F + f] = q;
+        }
+        __syncthreads();
+        if (tid < F) {
+            double q = 0.0;
+            for (int w = 0; w < W; ++w) q += red[w * F + tid];
+            a.sq_partial[(int64_t)b * F + tid] = q;
+        }
+    }
+}
+
+// ---- kernel timing for measurement tools -----------------------------------
+
+struct ProfileRec {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+};
+static ProfileRec g_prof;
+
+template <int FMT, int F>
+static int launch_one(const SpmmLaunch &L, hipStream_t st) {
+    const OpPlan &op = *L.op;
+    SpmmArgs a;
+    a.blk_stage = op.blk_stage;
+    a.blk_tile = op.blk_tile;
+    a.tile_list = op.tile_list;
+    a.slab = op.slab;
+    a.slot = op.slot;
+    a.val = op.val;
+    a.packed = op.packed;
+    a.xin = L.xin;
+    a.yout = L.yout;
+    a.scale = L.scale;
+    a.sq_partial = L.sq_partial;
+    a.n_row_tiles = op.n_row_tiles;
+    a.n_blocks = op.n_blocks;
+    a.T = op.T;
+    a.remap = L.remap;
+    typedef typename Stor<FMT>::T XT;
+    size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
+    const size_t red = sizeof(double) * (size_t)op.W * F;
+    if (smem < red) smem = red;
+    static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far
+    if ((int)smem > attr_bytes) {
+        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)smem));
+        attr_bytes = (int)smem;
+    }
+    const int grid = L.remap ? ((op.n_blocks + 7) / 8) * 8 : op.n_blocks;
+    if (grid == 0) return XCT_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof.on) {
+        XCT_HIP_TRY(hipEventCreate(&e0));
+        XCT_HIP_TRY(hipEventCreate(&e1));
+        XCT_HIP_TRY(hipEventRecord(e0, st));
+    }
+    hipLaunchKernelGGL((k_spmm<FMT, F>), dim3(grid), dim3(op.W * kTileSlots), smem, st, a);
+    XCT_HIP_TRY(hipGetLastError());
+    if (g_prof.on) {
+        XCT_HIP_TRY(hipEventRecord(e1, st));
+        g_prof.ev[op.which & 1].push_back({e0, e1});
+    }
+    return XCT_OK;
+}
+
+template <int FMT>
+static int launch_fmt(const SpmmLaunch &L, hipStream_t st) {
+    switch (L.F) {
+        case 1: return launch_one<FMT, 1>(L, st);
+        case 2: return launch_one<FMT, 2>(L, st);
+        case 4: return launch_one<FMT, 4>(L, st);
+        case 8: return launch_one<FMT, 8>(L, st);
+        case 16: return launch_one<FMT, 16>(L, st);
+        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    }
+}
+
+int launch_spmm(const SpmmLaunch &L, hipStream_t st) {
+    switch (L.vdt) {
+        case XCT_F32: return launch_fmt<XCT_F32>(L, st);
+        case XCT_F16: return launch_fmt<XCT_F16>(L, st);
+        case XCT_BF16: return launch_fmt<XCT_BF16>(L, st);
+        default: return fail(XCT_ERR_INVALID, "bad value dtype");
+    }
+}
+
+// ---- layout conversions -----------------------------------------------------
+
+__device__ __forceinline__ float load_io(const void *p, int64_t i, int io) {
+    if (io == XCT_F32) return ((const float *)p)[i];
+    const uint16_t b = ((const uint16_t *)p)[i];
+    return io == XCT_F16 ? h16_to_f32(b) : bf16_to_f32(b);
+}
+
+__device__ __forceinline__ uint32_t f32_to_h16(float v) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+}
+__device__ __forceinline__ uint32_t f32_to_bf16(float v) {
+    uint32_t u = __builtin_bit_cast(uint32_t, v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                  // nearest-even
+    return u >> 16;
+}
+
+__device__ __forceinline__ void store_io(void *p, int64_t i, float v, int io) {
+    if (io == XCT_F32)
+        ((float *)p)[i] = v;
+    else
+        ((uint16_t *)p)[i] = (uint16_t)(io == XCT_F16 ? f32_to_h16(v) : f32_to_bf16(v));
+}
+
+struct ConvArgs {
+    const int32_t *coord_of;
+    int64_t n_tiles;
+    int H, Wd, TW;
+    int batch, s0, F;
+    int io, storage;
+};
+
+__global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const float *inv) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= c.n_tiles * kTileSlots) return;
+    const int64_t rank = t >> 6;
+    const int o = (int)(t & 63);
+    const int coord = c.coord_of[rank];
+    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    const bool in = row < c.H && col < c.Wd;
+    const int64_t plane = (int64_t)c.H * c.Wd;
+    for (int f = 0; f < c.F; ++f) {
+        const int s = c.s0 + f;
+        float v = 0.f;
+        if (in && s < c.batch) {
+            v = load_io(nat, (int64_t)s * plane + (int64_t)row * c.Wd + col, c.io);
+            if (inv) v *= inv[f];
+        }
+        store_io(internal, t * c.F + f, v, c.storage);
+    }
+}
+
+__global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= c.n_tiles * kTileSlots) return;
+    const int64_t rank = t >> 6;
+    const int o = (int)(t & 63);
+    const int coord = c.coord_of[rank];
+    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    if (row >= c.H || col >= c.Wd) return;
+    const int64_t plane = (int64_t)c.H * c.Wd;
+    for (int f = 0; f < c.F; ++f) {
+        const int s = c.s0 + f;
+        if (s >= c.batch) break;
+        store_io(nat, (int64_t)s * plane + (int64_t)row * c.Wd + col, internal[t * c.F + f], c.io);
+    }
+}
+
+// Per-slice max |v| over the natural layout of one fused group.
+__global__ void k_absmax(const void *nat, int io, int64_t plane, int batch, int s0, int F, uint32_t *amax) {
+    const int f = blockIdx.y;
+    const int s = s0 + f;
+    if (s >= batch) return;
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(load_io(nat, (int64_t)s * plane + i, io)));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    __shared__ float wm[16];
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wm[w]);
+        atomicMax(&amax[f], __float_as_uint(m));  // non-negative floats order like their bits
+    }
+}
+
+// m = 2^ceil(log2 max) (1 for a zero or non-finite max), scale = m, inv = 1/m.
+// amax is cleared after it is read so the next group can reuse it.
+__global__ void k_pow2_scale(uint32_t *amax, int F, float *scale, float *inv) {
+    const int f = threadIdx.x;
+    if (f >= F) return;
+    const float mx = __uint_as_float(amax[f]);
+    amax[f] = 0u;
+    float m = 1.f;
+    if (mx > 0.f && mx <= 3.0e38f) {
+        int e;
+        const float mant = frexpf(mx, &e);  // mx = mant * 2^e, mant in [0.5, 1)
+        m = ldexpf(1.f, mant == 0.5f ? e - 1 : e);
+    }
+    scale[f] = m;
+    inv[f] = 1.f / m;  // exact: m is a power of two
+}
+
+static ConvArgs conv_args(const Grid &g, int batch, int s0, int F, int io, int storage) {
+    ConvArgs c;
+    c.coord_of = g.coord_of;
+    c.n_tiles = g.n_tiles;
+    c.H = g.H;
+    c.Wd = g.Wd;
+    c.TW = g.TW;
+    c.batch = batch;
+    c.s0 = s0;
+    c.F = F;
+    c.io = io;
+    c.storage = storage;
+    return c;
+}
+
+int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F, void *internal,
+                       xct_dtype storage, const float *inv_scale, hipStream_t st) {
+    const ConvArgs c = conv_args(g, batch, s0, F, io, storage);
+    const int64_t n = g.n_tiles * kTileSlots;
+    hipLaunchKernelGGL(k_to_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, nat, internal, inv_scale);
+    XCT_HIP_TRY(hipGetLastError());
+    return XCT_OK;
+}
+
+int launch_from_internal(const Grid &g, const float *internal, int batch, int s0, int F, void *nat, xct_dtype io,
+                         hipStream_t st) {
+    const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F32);
+    const int64_t n = g.n_tiles * kTileSlots;
+    hipLaunchKernelGGL(k_from_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, internal, nat);
+    XCT_HIP_TRY(hipGetLastError());
+    return XCT_OK;
+}
+
+int launch_pow2_scale(uint32_t *amax, int F, float *scale, float *inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(64), 0, st, amax, F, scale, inv);
+    XCT_HIP_TRY(hipGetLastError());
+    return XCT_OK;
+}
+
+int launch_natural_scale(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F, uint32_t *amax,
+                         float *scale, float *inv, hipStream_t st) {
+    const int64_t plane = (int64_t)g.H * g.Wd;
+    int blocks = (int)std::min<int64_t>(256, (plane + 1023) / 1024);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_absmax, dim3(blocks, F), dim3(1024), 0, st, nat, (int)io, plane, batch, s0, F, amax);
+    XCT_HIP_TRY(hipGetLastError());
+    return launch_pow2_scale(amax, F, scale, inv, st);
+}
+
+// ---- boundary entry points ---------------------------------------------------
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct SpmmWs {
+    void *in;
+    float *out;
+    uint32_t *amax;
+    float *scale, *inv;
+};
+
+static size_t spmm_ws_layout(const xct_matrix *m, int batch, char *base, SpmmWs *w) {
+    const int F = run_fuse(batch, m->fuse);
+    const int64_t tiles = std::max(m->vol.n_tiles, m->sino.n_tiles);
+    const size_t in_b = align256((size_t)tiles * kTileSlots * F * elem_bytes(m->vdt));
+    const size_t out_b = align256((size_t)tiles * kTileSlots * F * sizeof(float));
+    const size_t small = align256(sizeof(uint32_t) * 16) * 3;
+    if (w) {
+        w->in = base;
+        w->out = (float *)(base + in_b);
+        char *p = base + in_b + out_b;
+        w->amax = (uint32_t *)p;
+        w->scale = (float *)(p + align256(sizeof(uint32_t) * 16));
+        w->inv = (float *)(p + 2 * align256(sizeof(uint32_t) * 16));
+    }
+    return in_b + out_b + small;
+}
+
+static int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
+                     void *workspace, void *stream) {
+    if (!m || !src || !dst || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
+    if (!valid_dtype(io)) return fail(XCT_ERR_INVALID, "bad io dtype");
+    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const OpPlan &op = dir ? m->AT : m->A;
+    const Grid &gin = dir ? m->sino : m->vol;
+    const Grid &gout = dir ? m->vol : m->sino;
+    SpmmWs w;
+    spmm_ws_layout(m, batch, (char *)workspace, &w);
+    const int F = run_fuse(batch, m->fuse);
+    const bool norm = m->vdt != XCT_F32;
+    if (norm) XCT_HIP_TRY(hipMemsetAsync(w.amax, 0, sizeof(uint32_t) * 16, st));
+    for (int s0 = 0; s0 < batch; s0 += F) {
+        int rc;
+        if (norm) {
+            rc = launch_natural_scale(gin, src, io, batch, s0, F, w.amax, w.scale, w.inv, st);
+            if (rc) return rc;
+        }
+        rc = launch_to_internal(gin, src, io, batch, s0, F, w.in, m->vdt, norm ? w.inv : nullptr, st);
+        if (rc) return rc;
+        SpmmLaunch L{&op, w.in, w.out, norm ? w.scale : nullptr, nullptr, F, m->vdt, m->remap};
+        rc = launch_spmm(L, st);
+        if (rc) return rc;
+        rc = launch_from_internal(gout, w.out, batch, s0, F, dst, io, st);
+        if (rc) return rc;
+    }
+    return XCT_OK;
+}
+
+}  // namespace xct
+
+using namespace xct;
+
+extern "C" size_t xct_spmm_workspace_bytes(const xct_matrix *m, int batch) {
+    if (!m || batch < 1) return 0;
+    return spmm_ws_layout(m, batch, nullptr, nullptr);
+}
+
+extern "C" int xct_project(const xct_matrix *m, const void *x, void *y, int batch, xct_dtype io, void *workspace,
+                           void *stream) {
+    return spmm_call(m, 0, x, y, batch, io, workspace, stream);
+}
+
+extern "C" int xct_backproject(const xct_matrix *m, const void *y, void *x, int batch, xct_dtype io, void *workspace,
+                               void *stream) {
+    return spmm_call(m, 1, y, x, batch, io, workspace, stream);
+}
+
+extern "C" int xct_profile_enable(int on) {
+    g_prof.on = on != 0;
+    return XCT_OK;
+}
+
+extern "C" int xct_profile_read(int64_t *launches, double *ms) {
+    if (!launches || !ms) return fail(XCT_ERR_INVALID, "NULL argument");
+    int rc = XCT_OK;
+    for (int w = 0; w < 2; ++w) {
+        launches[w] = (int64_t)g_prof.ev[w].size();
+        ms[w] = 0.0;
+        for (auto &pr : g_prof.ev[w]) {
+            float t = 0.f;
+            hipError_t e = hipEventSynchronize(pr.second);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, pr.first, pr.second);
+            if (e != hipSuccess && rc == XCT_OK)
+                rc = fail(XCT_ERR_HIP, std::string("profile events: ") + hipGetErrorString(e));
+            ms[w] += t;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        g_prof.ev[w].clear();
+    }
+    return rc;
+}

@@ -1,0 +1,314 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: FP32 projection / backprojection within 1e-5 relative L2 per slice of
+the oracle on phantom inputs (the target fixed for the plain path); matrix
+entries equal to the oracle's FP64 lengths rounded once to the stored dtype
+(1 ulp allowed for the last-bit differences of device vs host sin/cos);
+FP32 CGLS within 1e-4 relative L2 of the FP64 oracle after a fixed count.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2009_07226_amd import phantoms
+
+pytestmark = pytest.mark.gpu
+
+xct = pytest.importorskip("paper_2009_07226_amd")
+
+_cache = {}
+
+
+def gpu_matrix(N, M, C, dt="f32", **kw):
+    key = (N, M, C, dt, tuple(sorted(kw.items())))
+    if key not in _cache:
+        _cache[key] = xct.Matrix(N, M, C, dt, **kw)
+    return _cache[key]
+
+
+def oracle_mats(N, M, C):
+    key = ("oracle", N, M, C)
+    if key not in _cache:
+        _cache[key] = (oracle.build_A(N, M, C), oracle.build_AT(N, M, C))
+    return _cache[key]
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+GEOMS = [(128, 180, 128), (37, 23, 41), (16, 12, 16), (24, 10, 23), (5, 7, 6), (64, 1, 64)]
+
+
+@pytest.mark.parametrize("N,M,C", GEOMS)
+@pytest.mark.parametrize("dt", ["f32", "f16", "bf16"])
+def test_matrix_entries_match_oracle(N, M, C, dt):
+    banner(f"entries N={N} M={M} C={C} {dt}")
+    A = gpu_matrix(N, M, C, dt)
+    Ao, ATo = oracle_mats(N, M, C)
+    npdt = {"f32": np.float32, "f16": np.float16, "bf16": None}[dt]
+    for which, ref in ((0, Ao.tocoo()), (1, ATo.tocoo())):
+        r, c, v = A.to_coo(which)
+        if dt == "bf16":
+            rv = torch.from_numpy(ref.data).to(torch.bfloat16).float().numpy()
+        else:
+            rv = ref.data.astype(npdt).astype(np.float32)
+        keep = rv != 0
+        rk = ref.row[keep].astype(np.int64) * ref.shape[1] + ref.col[keep]
+        gk = r.astype(np.int64) * ref.shape[1] + c
+        assert len(np.unique(gk)) == len(gk), "duplicate entries"
+        og, oo = np.argsort(gk), np.argsort(rk)
+        np.testing.assert_array_equal(gk[og], rk[oo])
+        gv, ov = v[og], rv[keep][oo]
+        if dt == "f32":
+            ulp = np.spacing(ov.astype(np.float32))
+        elif dt == "f16":
+            ulp = np.spacing(ov.astype(np.float16)).astype(np.float32)
+        else:
+            ulp = np.abs(ov) * 2.0 ** -7
+        assert np.all(np.abs(gv - ov) <= ulp), np.abs(gv - ov).max()
+        info = A.info()["AT" if which else "A"]
+        assert info["nnz"] == ref.nnz
+
+
+@pytest.mark.parametrize("N,M,C", GEOMS)
+@pytest.mark.parametrize("B", [1, 3, 16, 17])
+def test_project_backproject_parity(N, M, C, B):
+    banner(f"spmm N={N} M={M} C={C} B={B}")
+    A = gpu_matrix(N, M, C)
+    Ao, ATo = oracle_mats(N, M, C)
+    x = phantoms.ellipse_batch(N, B, 6, seed=100 + B).float()
+    y_gpu = xct.project(A, x.cuda()).cpu()
+    y_ref = oracle.project(Ao, x.double().numpy().reshape(B, -1))
+    e = rel_err(y_gpu.numpy(), y_ref)
+    assert e.max() <= 1e-5, e
+    yin = (torch.from_numpy(y_ref).float() + 0.1 * torch.randn(B, M * C, generator=torch.Generator().manual_seed(B)))
+    yin = yin.reshape(B, M, C)
+    xb_gpu = xct.backproject(A, yin.cuda()).cpu()
+    xb_ref = oracle.backproject(ATo, yin.double().numpy())
+    e = rel_err(xb_gpu.numpy(), xb_ref)
+    assert e.max() <= 1e-5, e
+
+
+def test_output_shape_and_zero_input():
+    A = gpu_matrix(37, 23, 41)
+    y = xct.project(A, torch.zeros(2, 37, 37, device="cuda"))
+    assert y.shape == (2, 23, 41) and float(y.abs().max()) == 0.0
+    x = xct.backproject(A, torch.zeros(2, 23, 41, device="cuda"))
+    assert x.shape == (2, 37, 37) and float(x.abs().max()) == 0.0
+
+
+def test_bitwise_deterministic_and_batch_independent():
+    N, M, C = 128, 180, 128
+    A = gpu_matrix(N, M, C)
+    x = phantoms.ellipse_batch(N, 16, 8, seed=5).float().cuda()
+    y1 = xct.project(A, x)
+    y2 = xct.project(A, x)
+    assert torch.equal(y1, y2)
+    # one slice alone through a 1-slice pass agrees with the fused pass
+    y3 = xct.project(A, x[5:6].contiguous())
+    e = (y3[0] - y1[5]).norm() / y1[5].norm()
+    assert float(e) <= 1e-6
+    b1 = xct.backproject(A, y1)
+    b2 = xct.backproject(A, y1)
+    assert torch.equal(b1, b2)
+
+
+def test_adjoint_identity_on_gpu():
+    N, M, C = 128, 180, 128
+    A = gpu_matrix(N, M, C)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn(4, N, N, device="cuda", generator=g)
+    y = torch.randn(4, M, C, device="cuda", generator=g)
+    Ax = xct.project(A, x).double()
+    ATy = xct.backproject(A, y).double()
+    lhs = (Ax * y.double()).sum(dim=(1, 2))
+    rhs = (x.double() * ATy).sum(dim=(1, 2))
+    scale = Ax.flatten(1).norm(dim=1) * y.double().flatten(1).norm(dim=1)
+    assert float(((lhs - rhs).abs() / scale).max()) <= 1e-6
+
+
+@pytest.mark.parametrize("dt,tol", [("f16", 2e-3), ("bf16", 1.5e-2)])
+def test_reduced_precision_projection_error(dt, tol):
+    N, M, C, B = 128, 180, 128, 4
+    A = gpu_matrix(N, M, C, dt)
+    Ao, ATo = oracle_mats(N, M, C)
+    x = phantoms.ellipse_batch(N, B, 8, seed=9).float()
+    y_ref = oracle.project(Ao, x.double().numpy().reshape(B, -1))
+    for io in (torch.float32, torch.float16 if dt == "f16" else torch.bfloat16):
+        y = xct.project(A, x.to(io).cuda()).float().cpu().numpy()
+        e = rel_err(y, y_ref)
+        banner(f"{dt} io={io} projection rel err {e.max():.2e}")
+        assert e.max() <= tol
+    yb = torch.from_numpy(y_ref.reshape(B, M, C)).float()
+    xb = xct.backproject(A, yb.cuda()).cpu().numpy()
+    e = rel_err(xb, oracle.backproject(ATo, yb.double().numpy()))
+    banner(f"{dt} backprojection rel err {e.max():.2e}")
+    assert e.max() <= tol
+
+
+def noisy_sinogram(Ao, x, sigma_frac, seed, M, C):
+    y = oracle.project(Ao, x.double().numpy().reshape(x.shape[0], -1))
+    sigma = sigma_frac * y.max()
+    nz = phantoms.noise((M * C,), range(x.shape[0]), seed)
+    return torch.from_numpy(y + sigma * nz).float().reshape(x.shape[0], M, C)
+
+
+CGLS_CASES = [(128, 180, 128, 1, 10), (37, 23, 41, 5, 8), (64, 90, 64, 17, 12)]
+
+
+def cgls_problem(N, M, C, B, seed=1):
+    Ao, ATo = oracle_mats(N, M, C)
+    x_true = phantoms.ellipse_batch(N, B, 10, seed=seed).float()
+    return Ao, ATo, x_true, noisy_sinogram(Ao, x_true, 0.01, seed, M, C)
+
+
+@pytest.mark.parametrize("N,M,C,B,iters", CGLS_CASES)
+def test_cgls_early_iterations_match_oracle(N, M, C, B, iters):
+    # Over the first iterations rounding has not yet been amplified by the
+    # recurrences (see test_cgls_iterates_amplify_rounding): tight parity.
+    banner(f"cgls early N={N} M={M} C={C} B={B}")
+    A = gpu_matrix(N, M, C)
+    Ao, ATo, _, y = cgls_problem(N, M, C, B)
+    for k in (1, 2, 4):
+        xg, resg, stg = xct.cgls(A, y.cuda(), k)
+        xo, reso, sto = oracle.cgls(Ao, ATo, y.double().numpy().reshape(B, -1), k)
+        e = rel_err(xg.cpu().numpy(), xo)
+        banner(f"  k={k} rel err {e.max():.2e}")
+        assert e.max() <= 1e-5, e
+        np.testing.assert_allclose(resg, reso, rtol=1e-5, atol=1e-8)
+        assert np.all(stg == sto)
+
+
+@pytest.mark.parametrize("N,M,C,B,iters", CGLS_CASES)
+def test_cgls_fixed_count_within_rounding_envelope(N, M, C, B, iters):
+    from cgls_envelope import envelope
+    banner(f"cgls fixed N={N} M={M} C={C} B={B} iters={iters}")
+    A = gpu_matrix(N, M, C)
+    Ao, ATo, x_true, y = cgls_problem(N, M, C, B)
+    yd = y.double().numpy().reshape(B, -1)
+    xg, resg, stg = xct.cgls(A, y.cuda(), iters)
+    xo, reso, sto = oracle.cgls(Ao, ATo, yd, iters)
+    dev = rel_err(xg.cpu().numpy(), xo)
+    env = envelope(Ao, ATo, yd, xo, iters, 8 * 2.0 ** -24)
+    banner(f"  deviation {dev.max():.2e} envelope {env.max():.2e}")
+    assert np.all(dev <= np.maximum(10 * env, 1e-5)), (dev, env)
+    assert np.all(stg == sto)
+    assert np.all(np.diff(resg, axis=0) <= 1e-6)  # CGLS residuals never grow
+    # the reconstruction is as good as the oracle's against the phantom
+    xt = x_true.double().numpy().reshape(B, -1)
+    assert np.all(rel_err(xg.cpu().numpy(), xt) <= 1.2 * rel_err(xo, xt))
+
+
+def test_cgls_zero_sinogram_slice_stops():
+    N, M, C, B = 37, 23, 41, 3
+    A = gpu_matrix(N, M, C)
+    Ao, _ = oracle_mats(N, M, C)
+    y = noisy_sinogram(Ao, phantoms.ellipse_batch(N, B, 5, seed=2).float(), 0.01, 2, M, C)
+    y[1] = 0
+    x, res, st = xct.cgls(A, y.cuda(), 6)
+    assert st[1] == 1 and st[0] == 0 and st[2] == 0
+    assert float(x[1].abs().max()) == 0.0 and np.all(res[:, 1] == 0.0)
+
+
+def test_cgls_zero_iterations():
+    N, M, C = 16, 12, 16
+    A = gpu_matrix(N, M, C)
+    y = torch.rand(2, M, C, device="cuda")
+    x, res, st = xct.cgls(A, y, 0)
+    assert float(x.abs().max()) == 0.0 and np.all(res[0] == 1.0)
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_cgls_reduced_precision_storage(dt):
+    from cgls_envelope import envelope
+    N, M, C, B = 128, 180, 128, 4
+    A16 = gpu_matrix(N, M, C, dt)
+    Ao, ATo, x_true, y = cgls_problem(N, M, C, B, seed=4)
+    yd = y.double().numpy().reshape(B, -1)
+    u = 2.0 ** -11 if dt == "f16" else 2.0 ** -8
+    # fixed count 3: within 1e-3 of the FP64 oracle (FP16 storage)
+    xg, _, _ = xct.cgls(A16, y.cuda(), 3)
+    xo, _, _ = oracle.cgls(Ao, ATo, yd, 3)
+    e = rel_err(xg.cpu().numpy(), xo)
+    banner(f"cgls {dt} 3 iterations rel err {e.max():.2e}")
+    if dt == "f16":
+        assert e.max() <= 1e-3, e
+    assert np.all(e <= np.maximum(10 * envelope(Ao, ATo, yd, xo, 3, u), 1e-5))
+    # fixed count 10: inside the rounding envelope of 16-bit storage
+    xg, resg, _ = xct.cgls(A16, y.cuda(), 10)
+    xo, reso, _ = oracle.cgls(Ao, ATo, yd, 10)
+    dev = rel_err(xg.cpu().numpy(), xo)
+    env = envelope(Ao, ATo, yd, xo, 10, u)
+    banner(f"cgls {dt} 10 iterations deviation {dev.max():.2e} envelope {env.max():.2e}")
+    assert np.all(dev <= np.maximum(10 * env, 1e-3))
+    xt = x_true.double().numpy().reshape(B, -1)
+    assert np.all(rel_err(xg.cpu().numpy(), xt) <= 1.2 * rel_err(xo, xt))
+
+
+def test_autograd_pair_matches_oracle_and_finite_differences():
+    N, M, C, B = 64, 90, 64, 2
+    A = gpu_matrix(N, M, C)
+    Ao, ATo = oracle_mats(N, M, C)
+    x_true = phantoms.ellipse_batch(N, B, 6, seed=7).float()
+    y = noisy_sinogram(Ao, x_true, 0.02, 7, M, C)
+    x0 = (0.5 * x_true).cuda().requires_grad_(True)
+    loss = 0.5 * ((xct.XctProject.apply(x0, A) - y.cuda()) ** 2).sum()
+    loss.backward()
+    g = x0.grad.double().cpu().numpy().reshape(B, -1)
+    xd = x0.detach().double().cpu().numpy().reshape(B, -1)
+    r = oracle.project(Ao, xd) - y.double().numpy().reshape(B, -1)
+    g_ref = oracle.backproject(ATo, r)
+    assert rel_err(g, g_ref).max() <= 1e-5
+    # central differences of the FP64 loss on 64 seeded voxels, h = 1e-3
+    rng = np.random.default_rng(0)
+    idx = rng.choice(N * N, 64, replace=False)
+    h = 1e-3
+    for b in range(B):
+        fd = []
+        for v in idx:
+            xp, xm = xd[b].copy(), xd[b].copy()
+            xp[v] += h
+            xm[v] -= h
+            lp = 0.5 * np.sum((oracle.project(Ao, xp[None])[0] - y[b].double().numpy().ravel()) ** 2)
+            lm = 0.5 * np.sum((oracle.project(Ao, xm[None])[0] - y[b].double().numpy().ravel()) ** 2)
+            fd.append((lp - lm) / (2 * h))
+        fd = np.array(fd)
+        assert np.linalg.norm(g[b, idx] - fd) <= 1e-4 * np.linalg.norm(fd)
+    # backprojection's backward is the projection
+    yv = y.cuda().requires_grad_(True)
+    out = xct.XctBackproject.apply(yv, A)
+    w = torch.randn_like(out)
+    (out * w).sum().backward()
+    ref = xct.project(A, w)
+    assert float((yv.grad - ref).abs().max()) == 0.0
+
+
+def test_sampled_rows_at_size_512():
+    # 8 slices of 512^2, 360 angles, 512 channels: sampled rows and voxels
+    # against the oracle traced one by one (the full CSR would be 1.4 GB).
+    N, M, C, B = 512, 360, 512, 8
+    banner("sampled parity N=512")
+    A = gpu_matrix(N, M, C)
+    x = phantoms.ellipsoid_phantom(N, B, 20, seed=3).float()
+    y = xct.project(A, x.cuda()).cpu()
+    rng = np.random.default_rng(11)
+    rows = rng.choice(M * C, 400, replace=False)
+    ref = oracle.project_rows(N, M, C, x.double().numpy(), rows)
+    got = y.reshape(B, -1)[:, rows].double().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    vox = rng.choice(N * N, 400, replace=False)
+    ys = torch.rand(B, M, C, generator=torch.Generator().manual_seed(12))
+    xb = xct.backproject(A, ys.cuda()).cpu()
+    ref = oracle.backproject_voxels(N, M, C, ys.double().numpy(), vox)
+    got = xb.reshape(B, -1)[:, vox].double().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()

@@ -1,0 +1,45 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads and exports
+every function include/xct.h declares; argument errors need no device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xct.h")
+LIB = os.path.join(ROOT, "paper_2009_07226_amd", "libxct.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xct_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("xct_build_matrix", "xct_project", "xct_backproject", "xct_cgls", "xct_free_matrix",
+                     "xct_matrix_info", "xct_last_error", "xct_cgls_workspace_bytes", "xct_spmm_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libxct.so has not been built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_errors_without_device():
+    import paper_2009_07226_amd as xct
+    L = xct.lib()
+    h = ctypes.c_void_p()
+    assert L.xct_build_matrix(0, 10, 10, 0, None, None, ctypes.byref(h)) == -1
+    assert b"n must be" in L.xct_last_error()
+    assert L.xct_build_matrix(8, 10, 10, 7, None, None, ctypes.byref(h)) == -1
+    assert L.xct_project(None, None, None, 1, 0, None, None) == -1
+    assert L.xct_cgls(None, None, 0, None, 1, 1, None, None, None, None) == -1
+    assert L.xct_spmm_workspace_bytes(None, 4) == 0
+    assert L.xct_cgls_workspace_bytes(None, 4, 3) == 0

@@ -291,3 +291,23 @@ def test_sampled_rows_and_voxels_match_full_products():
                                rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(oracle.backproject_voxels(N, M, C, y, vox), oracle.spmm(AT, y)[:, vox],
                                rtol=1e-13, atol=1e-13)
+
+
+def test_cgls_iterates_amplify_rounding():
+    """The reading behind the CGLS parity bars: on a 128^2, 180-angle scan with
+    1% noise, a relative perturbation of 1e-7 in every product (FP32-sized
+    rounding) leaves x_4 within 1e-5 of the exact iterate but moves x_10 by
+    more than 1e-3 -- so FP32 or FP16 CGLS can match the FP64 iterates tightly
+    only over the first iterations, and within the rounding envelope after."""
+    from cgls_envelope import envelope
+    from paper_2009_07226_amd import phantoms
+    N, M, C = 128, 180, 128
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    x_true = phantoms.ellipse_batch(N, 1, 10, seed=1)
+    y = oracle.project(A, x_true.numpy().reshape(1, -1))
+    y = y + 0.01 * y.max() * phantoms.noise((M * C,), [0], 1)
+    x4, _, _ = oracle.cgls(A, AT, y, 4)
+    x10, _, _ = oracle.cgls(A, AT, y, 10)
+    assert envelope(A, AT, y, x4, 4, 1e-7).max() < 1e-5
+    assert envelope(A, AT, y, x10, 10, 1e-7).max() > 1e-3
