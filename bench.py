@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--angles", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--stage-order", type=int, default=0, help="0 sweep (default), 1 Hilbert")
+    ap.add_argument("--lds-bytes", type=int, default=0)
+    ap.add_argument("--tile-waves", type=int, default=0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,7 +115,8 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     log(f"building FP32 matrix N={N} M={M} C={C}")
-    A = xct.Matrix(N, M, C, "f32")
+    opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves)
+    A = xct.Matrix(N, M, C, "f32", **opts)
     info = A.info()
     log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
         f"A^T padded {info['AT']['padded']:,}")
@@ -181,6 +185,10 @@ def main():
         "padded_A": info["A"]["padded"],
         "padded_AT": info["AT"]["padded"],
         "build_s_f32": round(info["build_seconds"], 3),
+        "plan": {"stages_A": info["A"]["stages"], "stages_AT": info["AT"]["stages"],
+                 "tiles_per_stage": info["A"]["tiles_per_stage"], "blocks_A": info["A"]["blocks"],
+                 "blocks_AT": info["AT"]["blocks"], "staged_slots_A": info["A"]["staged_slots"],
+                 "staged_slots_AT": info["AT"]["staged_slots"], "stage_order": args.stage_order},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_spmm<f32,16> (A and A^T launches)",
@@ -219,7 +227,7 @@ def main():
         del A
         torch.cuda.empty_cache()
         log("building FP16 matrix")
-        A16 = xct.Matrix(N, M, C, "f16")
+        A16 = xct.Matrix(N, M, C, "f16", **opts)
         log("CGLS FP16 storage")
         t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),

@@ -75,6 +75,10 @@ typedef struct {
                        default 81920 (two workgroups per CU) */
     int xcd_remap;  /* 1 (default): consecutive workgroups of the Hilbert order run on the
                        same XCD; -1: plain order */
+    int stage_order; /* order in which a workgroup stages its input tiles:
+                        0 (default) sweep: for A, by distance along the workgroup's mean ray
+                          direction; for A^T, angle-major;
+                        1 Hilbert: along the pseudo-Hilbert curve of the input tiles */
 } xct_build_opts;
 
 /* Statistics of one operator (A or A^T). */

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <type_traits>
@@ -132,20 +133,22 @@ static void hilbert_ranks(int TH, int TW, std::vector<int32_t> &rank_of, std::ve
 
 // Rows of A: row tile = sinogram tile (8 angles x 8 channels); inputs are
 // voxel tiles.
+// Each generator visits the entries of one row as (key, offset, length):
+// key = key_of[raster index of the input tile], the input tile's place in
+// the block's staging order; offset = slot within the 8 x 8 tile.
 struct ProjRows {
     int N, M, C;
     const int32_t *row_coord;  // sinogram rank -> raster tile
     int rowTW;                 // sinogram tiles per tile row
-    const int32_t *in_rank;    // voxel raster tile -> rank
-    int inTW;
+    int inTW;                  // voxel tiles per tile row
     template <class V>
-    __device__ __forceinline__ void run(int64_t rt, int lane, V &&v) const {
+    __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
         const int k = (coord / rowTW) * kTile + (lane >> 3);
         const int c = (coord % rowTW) * kTile + (lane & 7);
         if (k >= M || c >= C) return;
         trace_ray(N, M, C, k, c, [&](int i, int j, double len) {
-            v(in_rank[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
+            v(key_of[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
         });
     }
 };
@@ -155,18 +158,29 @@ struct BackRows {
     int N, M, C;
     const int32_t *row_coord;  // voxel rank -> raster tile
     int rowTW;
-    const int32_t *in_rank;    // sinogram raster tile -> rank
-    int inTW;
+    int inTW;                  // sinogram tiles per tile row
     template <class V>
-    __device__ __forceinline__ void run(int64_t rt, int lane, V &&v) const {
+    __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
         const int i = (coord / rowTW) * kTile + (lane >> 3);
         const int j = (coord % rowTW) * kTile + (lane & 7);
         if (i >= N || j >= N) return;
         trace_voxel(N, M, C, i, j, [&](int k, int c, double len) {
-            v(in_rank[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
+            v(key_of[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
         });
     }
+};
+
+// Staging order of the input tiles of a block.  Class q of the block selects
+// a permutation of the input tiles: key_of[q][raster] is a tile's place in
+// the order and tile_of[q][key] its internal (Hilbert-rank) index.  A block
+// stages the tiles it touches in increasing key.
+struct StageOrder {
+    const int32_t *key_of;
+    const int32_t *tile_of;
+    const int32_t *blk_class;  // [n_blocks] or nullptr (class 0 everywhere)
+    int64_t n_in;
+    __device__ __forceinline__ int64_t base(int b) const { return blk_class ? (int64_t)blk_class[b] * n_in : 0; }
 };
 
 // ---- builder kernels --------------------------------------------------------
@@ -192,8 +206,8 @@ __device__ __forceinline__ BuildLds carve(void *smem, int nwords, int nthr) {
 }
 
 template <class Rows>
-__device__ void mark_tiles(const Rows &rows, int64_t n_row_tiles, const BuildLds &L, int nwords,
-                           int64_t *entries) {
+__device__ void mark_tiles(const Rows &rows, const int32_t *key_of, int64_t n_row_tiles, const BuildLds &L,
+                           int nwords, int64_t *entries) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int w = tid; w < nwords; w += nthr) L.bits[w] = 0u;
     __syncthreads();
@@ -202,12 +216,12 @@ __device__ void mark_tiles(const Rows &rows, int64_t n_row_tiles, const BuildLds
     int64_t n = 0;
     if (rt < n_row_tiles) {
         int last = -1;
-        rows.run(rt, tid & 63, [&](int rank, int, double) {
+        rows.run(rt, tid & 63, key_of, [&](int key, int, double) {
             ++n;
-            if (rank == last) return;
-            last = rank;
-            const uint32_t m = 1u << (rank & 31);
-            if (!(L.bits[rank >> 5] & m)) atomicOr(&L.bits[rank >> 5], m);
+            if (key == last) return;
+            last = key;
+            const uint32_t m = 1u << (key & 31);
+            if (!(L.bits[key >> 5] & m)) atomicOr(&L.bits[key >> 5], m);
         });
     }
     if (entries) *entries = n;
@@ -262,11 +276,12 @@ __device__ __forceinline__ int tile_pos(const BuildLds &L, int rank) {
 }
 
 template <class Rows>
-__global__ void k_footprint(Rows rows, int64_t n_row_tiles, int nwords, int32_t *ntiles, int64_t *nnz) {
+__global__ void k_footprint(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int32_t *ntiles,
+                            int64_t *nnz) {
     extern __shared__ __align__(16) char smem[];
     const BuildLds L = carve(smem, nwords, blockDim.x);
     int64_t e = 0;
-    mark_tiles(rows, n_row_tiles, L, nwords, &e);
+    mark_tiles(rows, ord.key_of + ord.base(blockIdx.x), n_row_tiles, L, nwords, &e);
     int64_t t = 0;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) t += __popc(L.bits[w]);
     const int64_t tiles = block_sum(L, t);
@@ -283,14 +298,17 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 template <class Rows>
-__global__ void k_plan(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW, const int32_t *blk_tile,
-                       const int32_t *blk_stage, int32_t *tile_list, int32_t *stage_len, int *err) {
+__global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW,
+                       const int32_t *blk_tile, const int32_t *blk_stage, int32_t *tile_list, int32_t *stage_len,
+                       int *err) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6;
     const BuildLds L = carve(smem, nwords, nthr);
-    mark_tiles(rows, n_row_tiles, L, nwords, nullptr);
-    build_prefix(L, nwords);
     const int b = blockIdx.x;
+    const int32_t *key_of = ord.key_of + ord.base(b);
+    const int32_t *tile_of = ord.tile_of + ord.base(b);
+    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr);
+    build_prefix(L, nwords);
     const int base = blk_tile[b];
     const int ntl = blk_tile[b + 1] - base;
     for (int w = tid; w < nwords; w += nthr) {
@@ -302,7 +320,7 @@ __global__ void k_plan(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW
                 atomicOr(err, 2);
                 break;
             }
-            tile_list[base + p++] = w * 32 + bit;
+            tile_list[base + p++] = tile_of[w * 32 + bit];
             m &= m - 1u;
         }
     }
@@ -312,8 +330,8 @@ __global__ void k_plan(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW
         for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
         __syncthreads();
         if (rt < n_row_tiles) {
-            rows.run(rt, tid & 63, [&](int rank, int, double) {
-                const int st = tile_pos(L, rank) / T - s0;
+            rows.run(rt, tid & 63, key_of, [&](int key, int, double) {
+                const int st = tile_pos(L, key) / T - s0;
                 if (st >= 0 && st < SW && s0 + st < nst) L.cnt[st * nthr + tid] += 1;
             });
         }
@@ -329,22 +347,24 @@ __global__ void k_plan(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW
 }
 
 template <class Rows, int FMT>
-__global__ void k_fill(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW, const int32_t *blk_stage,
-                       const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed, int *err) {
+__global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW, int swz,
+                       const int32_t *blk_stage, const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed,
+                       int *err) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6, lane = tid & 63;
     const BuildLds L = carve(smem, nwords, nthr);
-    mark_tiles(rows, n_row_tiles, L, nwords, nullptr);
-    build_prefix(L, nwords);
     const int b = blockIdx.x;
+    const int32_t *key_of = ord.key_of + ord.base(b);
+    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr);
+    build_prefix(L, nwords);
     const int nst = blk_stage[b + 1] - blk_stage[b];
     const int64_t rt = (int64_t)b * W + wave;
     for (int s0 = 0; s0 < nst; s0 += SW) {
         for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
         __syncthreads();
         if (rt < n_row_tiles) {
-            rows.run(rt, lane, [&](int rank, int off, double len) {
-                const int pos = tile_pos(L, rank);
+            rows.run(rt, lane, key_of, [&](int key, int off, double len) {
+                const int pos = tile_pos(L, key);
                 const int st = pos / T;
                 const int sl = st - s0;
                 if (sl < 0 || sl >= SW) return;
@@ -360,7 +380,7 @@ __global__ void k_fill(Rows rows, int64_t n_row_tiles, int nwords, int T, int SW
                     return;
                 }
                 const int64_t idx = (g * kTileSlots + lane) * kGroup + (n % kGroup);
-                const uint32_t s = (uint32_t)((pos % T) * kTileSlots + off);
+                const uint32_t s = lds_swizzle((uint32_t)((pos % T) * kTileSlots + off), swz);
                 if (FMT == XCT_F32) {
                     slot[idx] = (uint16_t)s;
                     val[idx] = (float)len;
@@ -397,11 +417,115 @@ static int make_grid(Grid &g, int H, int Wd) {
     g.TH = (H + kTile - 1) / kTile;
     g.TW = (Wd + kTile - 1) / kTile;
     g.n_tiles = (int64_t)g.TH * g.TW;
-    std::vector<int32_t> rank_of, coord_of;
-    hilbert_ranks(g.TH, g.TW, rank_of, coord_of);
-    int rc = upload(&g.rank_of, rank_of);
+    hilbert_ranks(g.TH, g.TW, g.h_rank_of, g.h_coord_of);
+    int rc = upload(&g.rank_of, g.h_rank_of);
     if (rc) return rc;
-    return upload(&g.coord_of, coord_of);
+    return upload(&g.coord_of, g.h_coord_of);
+}
+
+// ---- staging orders -------------------------------------------------------
+
+constexpr int kSweepClasses = 64;  // direction classes of the projection sweep order
+
+struct HostOrder {
+    std::vector<int32_t> key_of, tile_of, blk_class;
+    int n_class = 1;
+};
+
+// Hilbert order: the key is the tile's Hilbert rank, which is also its
+// internal index.
+static void order_hilbert(const Grid &in, HostOrder &o) {
+    o.n_class = 1;
+    o.key_of = in.h_rank_of;
+    o.tile_of.resize(in.n_tiles);
+    for (int64_t r = 0; r < in.n_tiles; ++r) o.tile_of[r] = (int32_t)r;
+}
+
+// Raster order of the input grid (for A^T: sinogram tiles angle-major, so a
+// stage covers whole channel ranges of consecutive angles and every voxel of
+// a wavefront finds about the same number of entries in it).
+static void order_raster(const Grid &in, HostOrder &o) {
+    o.n_class = 1;
+    o.key_of.resize(in.n_tiles);
+    o.tile_of.resize(in.n_tiles);
+    for (int64_t t = 0; t < in.n_tiles; ++t) {
+        o.key_of[t] = (int32_t)t;
+        o.tile_of[t] = in.h_rank_of[t];
+    }
+}
+
+// Sweep order for A: voxel tiles sorted by the distance of their centre
+// along a ray direction, one order per direction class; a block uses the
+// class of its rays' mean angle.  A stage is then a band across the block's
+// (nearly parallel) rays and every ray of a wavefront crosses it with about
+// the same number of voxels, which keeps the ELL slabs short.
+static void order_sweep_proj(const xct_matrix *m, int W, int n_blocks, HostOrder &o) {
+    const Grid &in = m->vol, &rows = m->sino;
+    const int Q = kSweepClasses;
+    o.n_class = Q;
+    const int64_t n = in.n_tiles;
+    o.key_of.resize((size_t)Q * n);
+    o.tile_of.resize((size_t)Q * n);
+    std::vector<std::pair<double, int32_t>> key(n);
+    for (int q = 0; q < Q; ++q) {
+        const double th = M_PI * (q + 0.5) / Q;
+        const double dx = -std::sin(th), dy = std::cos(th);
+        for (int64_t t = 0; t < n; ++t) {
+            const int ty = (int)(t / in.TW), tx = (int)(t % in.TW);
+            key[t] = {(tx + 0.5) * dx + (ty + 0.5) * dy, in.h_rank_of[t]};
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t p = 0; p < n; ++p) {
+            const int32_t rank = key[p].second;
+            const int32_t raster = in.h_coord_of[rank];
+            o.key_of[(size_t)q * n + raster] = (int32_t)p;
+            o.tile_of[(size_t)q * n + p] = rank;
+        }
+    }
+    o.blk_class.resize(n_blocks);
+    for (int b = 0; b < n_blocks; ++b) {
+        double sc = 0.0, ss = 0.0;
+        for (int w = 0; w < W; ++w) {
+            const int64_t rt = (int64_t)b * W + w;
+            if (rt >= rows.n_tiles) break;
+            const int ta = rows.h_coord_of[rt] / rows.TW;
+            for (int k = ta * kTile; k < std::min(m->M, ta * kTile + kTile); ++k) {
+                const double th = M_PI * k / m->M;
+                sc += std::cos(2.0 * th);
+                ss += std::sin(2.0 * th);
+            }
+        }
+        double th = 0.5 * std::atan2(ss, sc);
+        if (th < 0) th += M_PI;
+        int q = (int)(th / M_PI * Q);
+        o.blk_class[b] = q < 0 ? 0 : (q >= Q ? Q - 1 : q);
+    }
+}
+
+struct DevOrder {
+    StageOrder d{};
+    void *bufs[3] = {nullptr, nullptr, nullptr};
+    ~DevOrder() {
+        for (void *p : bufs)
+            if (p) (void)hipFree(p);
+    }
+};
+
+static int upload_order(const HostOrder &h, int64_t n_in, DevOrder &d) {
+    int32_t *k = nullptr, *t = nullptr, *c = nullptr;
+    int rc = upload(&k, h.key_of);
+    d.bufs[0] = k;
+    if (!rc) rc = upload(&t, h.tile_of);
+    d.bufs[1] = t;
+    if (!rc && !h.blk_class.empty()) {
+        rc = upload(&c, h.blk_class);
+        d.bufs[2] = c;
+    }
+    d.d.key_of = k;
+    d.d.tile_of = t;
+    d.d.blk_class = c;
+    d.d.n_in = n_in;
+    return rc;
 }
 
 static void free_op(OpPlan &op) {
@@ -412,9 +536,10 @@ static void free_op(OpPlan &op) {
 }
 
 template <class Rows>
-static int build_op(OpPlan &op, const Rows &rows, int64_t n_row_tiles, int64_t n_in_tiles, int W, int T,
-                    xct_dtype vdt, hipStream_t st) {
+static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t n_row_tiles, int64_t n_in_tiles,
+                    int W, int T, int swz, xct_dtype vdt, hipStream_t st) {
     op.which = std::is_same<Rows, BackRows>::value ? 1 : 0;
+    op.swz = swz;
     op.n_row_tiles = n_row_tiles;
     op.n_in_tiles = n_in_tiles;
     op.W = W;
@@ -439,7 +564,7 @@ static int build_op(OpPlan &op, const Rows &rows, int64_t n_row_tiles, int64_t n
     XCT_HIP_TRY(hipMalloc(&d_nnz.p, sizeof(int64_t) * nb));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_footprint<Rows>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_mark));
-    hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, n_row_tiles, nwords,
+    hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, ord, n_row_tiles, nwords,
                        (int32_t *)d_nt.p, (int64_t *)d_nnz.p);
     XCT_HIP_TRY(hipGetLastError());
     std::vector<int32_t> nt(nb);
@@ -472,7 +597,7 @@ static int build_op(OpPlan &op, const Rows &rows, int64_t n_row_tiles, int64_t n
     XCT_HIP_TRY(hipMemsetAsync(d_err.p, 0, sizeof(int), st));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_plan<Rows>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)smem_win));
-    hipLaunchKernelGGL(k_plan<Rows>, dim3(nb), dim3(nthr), smem_win, st, rows, n_row_tiles, nwords, T, SW,
+    hipLaunchKernelGGL(k_plan<Rows>, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW,
                        op.blk_tile, op.blk_stage, op.tile_list, (int32_t *)d_len.p, (int *)d_err.p);
     XCT_HIP_TRY(hipGetLastError());
     std::vector<int32_t> len(nlen);
@@ -497,7 +622,7 @@ static int build_op(OpPlan &op, const Rows &rows, int64_t n_row_tiles, int64_t n
     auto fill = [&](auto kern) -> int {
         XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem_win));
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, n_row_tiles, nwords, T, SW,
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW, op.swz,
                            op.blk_stage, op.slab, op.slot, op.val, op.packed, (int *)d_err.p);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
@@ -543,6 +668,8 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (n_angles < 1 || n_angles > 30000) return fail(XCT_ERR_INVALID, "n_angles must be in [1, 30000]");
     if (n_channels < 1 || n_channels > 16384) return fail(XCT_ERR_INVALID, "n_channels must be in [1, 16384]");
     if (!valid_dtype(value_dtype)) return fail(XCT_ERR_INVALID, "bad value dtype");
+    if (opts && (opts->stage_order < 0 || opts->stage_order > 1))
+        return fail(XCT_ERR_INVALID, "stage_order must be 0 (sweep) or 1 (Hilbert)");
     xct_build_opts o = {};
     if (opts) o = *opts;
     const int W = o.tile_waves ? o.tile_waves : 8;
@@ -561,6 +688,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (lds < per_tile || lds > lds_max) return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
     int T = lds / per_tile;
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
+    const int swz = lds_swizzle_bits(F * elem_bytes(value_dtype));
     auto t0 = std::chrono::steady_clock::now();
     xct_matrix *m = new xct_matrix();
     m->n = n;
@@ -573,12 +701,27 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     int rc = make_grid(m->vol, n, n);
     if (!rc) rc = make_grid(m->sino, n_angles, n_channels);
     if (!rc) {
-        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.rank_of, m->vol.TW};
-        rc = build_op(m->A, pr, m->sino.n_tiles, m->vol.n_tiles, W, T, value_dtype, st);
+        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.TW};
+        HostOrder ho;
+        const int nb = (int)((m->sino.n_tiles + W - 1) / W);
+        if (o.stage_order == 1)
+            order_hilbert(m->vol, ho);
+        else
+            order_sweep_proj(m, W, nb, ho);
+        DevOrder dord;
+        rc = upload_order(ho, m->vol.n_tiles, dord);
+        if (!rc) rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, swz, value_dtype, st);
     }
     if (!rc) {
-        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.rank_of, m->sino.TW};
-        rc = build_op(m->AT, br, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, st);
+        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW};
+        HostOrder ho;
+        if (o.stage_order == 1)
+            order_hilbert(m->sino, ho);
+        else
+            order_raster(m->sino, ho);
+        DevOrder dord;
+        rc = upload_order(ho, m->sino.n_tiles, dord);
+        if (!rc) rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, swz, value_dtype, st);
     }
     if (rc) {
         std::string msg = g_last_error;
@@ -695,7 +838,10 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
                             }
                             if (rt >= op.n_row_tiles)
                                 return fail(XCT_ERR_INTERNAL, "entry in a padding row tile");
-                            const int pos = (int)(sidx / kTileSlots), off = (int)(sidx % kTileSlots);
+                            // the placement XORs low bits with a function of bits it leaves
+                            // unchanged, so it is its own inverse
+                            const uint32_t logical = lds_swizzle(sidx, op.swz);
+                            const int pos = (int)(logical / kTileSlots), off = (int)(logical % kTileSlots);
                             if (pos >= nt) return fail(XCT_ERR_INTERNAL, "slot outside its stage");
                             const int rco = rcoord[rt];
                             const int r_row = (rco / rg.TW) * kTile + (lane >> 3);

@@ -37,6 +37,7 @@ struct OpPlan {
     int W = 0;  // row tiles (wavefronts) per block
     int T = 0;  // input tiles per stage
     int n_blocks = 0;
+    int swz = 0;  // lds_swizzle bits used for the stored slots
     int64_t n_stages = 0;
     int64_t n_groups = 0;
     int64_t n_list = 0;
@@ -50,6 +51,27 @@ struct OpPlan {
     int64_t nnz = 0, padded = 0, staged_slots = 0, bytes = 0;
 };
 
+// LDS row placement of the staged input.  A stage holds T*64 rows of
+// F*elem bytes; with L = 2^k rows per 256-byte LDS line the row of slot s is
+// placed at s ^ ((s >> k) & (L-1)) ^ ((s >> 2k) & (L-1)), a permutation within
+// aligned groups of L rows.  Neighbouring rays visit slots that differ in
+// low bits (adjacent columns) or in bits k.. (adjacent rows); the XOR spreads
+// both cases over the banks.  Entries store the placed (physical) slot.  The
+// map XORs the low k bits with a function of higher bits it leaves unchanged,
+// so it is its own inverse.
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t s, int k) {
+    if (k <= 0) return s;
+    const uint32_t m = (1u << k) - 1u;
+    return s ^ ((s >> k) & m) ^ ((s >> (2 * k)) & m);
+}
+// k for rows of row_bytes bytes (0 when a row fills a line or is below 16 B).
+inline int lds_swizzle_bits(int row_bytes) {
+    if (row_bytes < 16 || row_bytes >= 256) return 0;
+    int k = 0;
+    while ((row_bytes << (k + 1)) <= 256) ++k;
+    return k;
+}
+
 // Geometry of one tiled 2D grid (H rows x Wd columns).
 struct Grid {
     int H = 0, Wd = 0;
@@ -57,6 +79,7 @@ struct Grid {
     int64_t n_tiles = 0;
     int32_t *rank_of = nullptr;    // [TH*TW] raster tile -> Hilbert rank (device)
     int32_t *coord_of = nullptr;   // [n_tiles] Hilbert rank -> raster tile (device)
+    std::vector<int32_t> h_rank_of, h_coord_of;  // host copies
 };
 
 }  // namespace xct

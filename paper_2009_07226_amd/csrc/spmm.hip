@@ -47,50 +47,46 @@ template <> struct Stor<XCT_F32> { typedef float T; };
 template <> struct Stor<XCT_F16> { typedef uint16_t T; };
 template <> struct Stor<XCT_BF16> { typedef uint16_t T; };
 
-// Read the F operands of one LDS row as FP32.
+// Shape of one staged row (the F operands of one slot).
 template <int FMT, int F>
-__device__ __forceinline__ void lds_row(const typename Stor<FMT>::T *row, float (&x)[F]) {
+struct RowShape {
+    typedef typename Stor<FMT>::T XT;
+    static constexpr int RB = F * (int)sizeof(XT);   // bytes per row
+    static constexpr int CH = RB >= 16 ? RB / 16 : 1; // 16-byte chunks per row (rows below 16 B: one piece)
+    static constexpr int SPC = F / CH;                // slices per chunk
+};
+
+// Expand one 16-byte chunk (or a sub-16-byte row) into SPC FP32 values.
+template <int FMT, int SPC>
+__device__ __forceinline__ void expand(const u32x4 w, float (&x)[SPC]) {
     if constexpr (FMT == XCT_F32) {
-        if constexpr (F >= 4) {
+        const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-            for (int q = 0; q < F / 4; ++q) {
-                const f32x4 v = ((const f32x4 *)row)[q];
-                x[4 * q + 0] = v.x;
-                x[4 * q + 1] = v.y;
-                x[4 * q + 2] = v.z;
-                x[4 * q + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int f = 0; f < F; ++f) x[f] = row[f];
-        }
+        for (int t = 0; t < SPC; ++t) x[t] = __builtin_bit_cast(float, u[t]);
     } else {
-        constexpr int words = (F + 1) / 2;  // 32-bit words holding F 16-bit values
-        uint32_t w[words];
-        if constexpr (words >= 4) {
+        const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-            for (int q = 0; q < words / 4; ++q) {
-                const u32x4 v = ((const u32x4 *)row)[q];
-                w[4 * q + 0] = v.x;
-                w[4 * q + 1] = v.y;
-                w[4 * q + 2] = v.z;
-                w[4 * q + 3] = v.w;
-            }
-        } else if constexpr (words == 2) {
-            const u32x2 v = *(const u32x2 *)row;
-            w[0] = v.x;
-            w[1] = v.y;
-        } else if constexpr (F == 2) {
-            w[0] = *(const uint32_t *)row;
-        } else {
-            w[0] = *(const uint16_t *)row;
-        }
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            const uint32_t b = (f & 1) ? (w[f >> 1] >> 16) : (w[f >> 1] & 0xffffu);
-            x[f] = FMT == XCT_F16 ? h16_to_f32(b) : bf16_to_f32(b);
+        for (int t = 0; t < SPC; ++t) {
+            const uint32_t b = (t & 1) ? (u[t >> 1] >> 16) : (u[t >> 1] & 0xffffu);
+            x[t] = FMT == XCT_F16 ? h16_to_f32(b) : bf16_to_f32(b);
         }
     }
+}
+
+// Load a row of fewer than 16 bytes.
+template <int RB>
+__device__ __forceinline__ u32x4 load_small(const char *p) {
+    u32x4 w = {0u, 0u, 0u, 0u};
+    if constexpr (RB == 8) {
+        const u32x2 v = *(const u32x2 *)p;
+        w.x = v.x;
+        w.y = v.y;
+    } else if constexpr (RB == 4) {
+        w.x = *(const uint32_t *)p;
+    } else {
+        w.x = *(const uint16_t *)p;
+    }
+    return w;
 }
 
 struct SpmmArgs {
@@ -104,14 +100,72 @@ struct SpmmArgs {
     const float *scale;
     double *sq_partial;
     int64_t n_row_tiles;
-    int n_blocks, T, remap;
+    int n_blocks, T, remap, swz;
 };
+
+// One group: kGroup consecutive ELL steps of one lane.
+template <int FMT> struct Group;
+template <> struct Group<XCT_F32> { u32x2 s; f32x4 v; };
+template <> struct Group<XCT_F16> { u32x4 p; };
+template <> struct Group<XCT_BF16> { u32x4 p; };
+
+template <int FMT>
+__device__ __forceinline__ Group<FMT> load_group(const SpmmArgs &a, int64_t e) {
+    Group<FMT> g;
+    if constexpr (FMT == XCT_F32) {
+        g.s = __builtin_nontemporal_load((const u32x2 *)a.slot + e);
+        g.v = __builtin_nontemporal_load((const f32x4 *)a.val + e);
+    } else {
+        g.p = __builtin_nontemporal_load((const u32x4 *)a.packed + e);
+    }
+    return g;
+}
+
+template <int FMT, int F>
+__device__ __forceinline__ void use_group(const Group<FMT> &g, const char *lds, const int (&coff)[RowShape<FMT, F>::CH],
+                                          float (&acc)[F]) {
+    typedef RowShape<FMT, F> R;
+    uint32_t sl[kGroup];
+    float v[kGroup];
+    if constexpr (FMT == XCT_F32) {
+        sl[0] = g.s.x & 0xffffu;
+        sl[1] = g.s.x >> 16;
+        sl[2] = g.s.y & 0xffffu;
+        sl[3] = g.s.y >> 16;
+        v[0] = g.v.x;
+        v[1] = g.v.y;
+        v[2] = g.v.z;
+        v[3] = g.v.w;
+    } else {
+        const uint32_t p[4] = {g.p.x, g.p.y, g.p.z, g.p.w};
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            sl[q] = p[q] >> 16;
+            v[q] = FMT == XCT_F16 ? h16_to_f32(p[q] & 0xffffu) : bf16_to_f32(p[q] & 0xffffu);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+        const char *row = lds + sl[q] * R::RB;
+#pragma unroll
+        for (int j = 0; j < R::CH; ++j) {
+            u32x4 w;
+            if constexpr (R::RB >= 16)
+                w = *(const u32x4 *)(row + coff[j]);
+            else
+                w = load_small<R::RB>(row);
+            float x[R::SPC];
+            expand<FMT, R::SPC>(w, x);
+#pragma unroll
+            for (int t = 0; t < R::SPC; ++t) acc[j * R::SPC + t] = fmaf(v[q], x[t], acc[j * R::SPC + t]);
+        }
+    }
+}
 
 template <int FMT, int F>
 __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
-    typedef typename Stor<FMT>::T XT;
+    typedef RowShape<FMT, F> R;
     extern __shared__ __align__(16) char smem[];
-    XT *lds = (XT *)smem;
     const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6;
     const int wave = tid >> 6, lane = tid & 63;
     int b = blockIdx.x;
@@ -121,74 +175,101 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     }
     if (b >= a.n_blocks) return;  // whole workgroup, before any barrier
 
+    // Lane l reads chunk (j + l) mod CH of a row at sub-step j, so the lanes
+    // of one LDS cycle spread over the chunks; accumulator block j holds the
+    // slices of that rotated chunk.
+    int coff[R::CH];
+#pragma unroll
+    for (int j = 0; j < R::CH; ++j) coff[j] = ((j + lane) & (R::CH - 1)) * 16;
     float acc[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) acc[f] = 0.f;
 
-    constexpr int kVecPerTile = kTileSlots * F * (int)sizeof(XT) / 16;  // 16-byte chunks per tile
+    constexpr int kVecPerTile = kTileSlots * R::RB / 16;  // 16-byte vectors per staged tile
     const int s0 = a.blk_stage[b], s1 = a.blk_stage[b + 1];
     const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
     const u32x4 *xin = (const u32x4 *)a.xin;
-    u32x4 *ldsv = (u32x4 *)smem;
     for (int s = s0; s < s1; ++s) {
         const int q0 = t0 + (s - s0) * a.T;
         const int nt = min(a.T, t1 - q0);
+        const int64_t g0 = a.slab[(int64_t)s * W + wave], g1 = a.slab[(int64_t)s * W + wave + 1];
+        // The first groups of this stage are requested before the staging
+        // round so their latency overlaps it; afterwards each consumed group
+        // is replaced by the one four places ahead.
+        Group<FMT> e0, e1, e2, e3;
+        if (g0 < g1) e0 = load_group<FMT>(a, g0 * kTileSlots + lane);
+        if (g0 + 1 < g1) e1 = load_group<FMT>(a, (g0 + 1) * kTileSlots + lane);
+        if (g0 + 2 < g1) e2 = load_group<FMT>(a, (g0 + 2) * kTileSlots + lane);
+        if (g0 + 3 < g1) e3 = load_group<FMT>(a, (g0 + 3) * kTileSlots + lane);
         __syncthreads();  // previous stage fully consumed
         for (int e = tid; e < nt * kVecPerTile; e += nthr) {
             const int q = e / kVecPerTile, r = e % kVecPerTile;
-            const int tile = a.tile_list[q0 + q];
-            ldsv[e] = xin[(int64_t)tile * kVecPerTile + r];
-        }
-        __syncthreads();
-        const int64_t g0 = a.slab[(int64_t)s * W + wave], g1 = a.slab[(int64_t)s * W + wave + 1];
-        for (int64_t g = g0; g < g1; ++g) {
-            const int64_t e = g * kTileSlots + lane;
-            uint32_t sl[kGroup];
-            float v[kGroup];
-            if constexpr (FMT == XCT_F32) {
-                const u32x2 s2 = __builtin_nontemporal_load((const u32x2 *)a.slot + e);
-                const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)a.val + e);
-                sl[0] = s2.x & 0xffffu;
-                sl[1] = s2.x >> 16;
-                sl[2] = s2.y & 0xffffu;
-                sl[3] = s2.y >> 16;
-                v[0] = v4.x;
-                v[1] = v4.y;
-                v[2] = v4.z;
-                v[3] = v4.w;
+            const u32x4 v = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + r];
+            if constexpr (R::RB >= 16) {
+                const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
+                ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v;
             } else {
-                const u32x4 p4 = __builtin_nontemporal_load((const u32x4 *)a.packed + e);
-                const uint32_t p[4] = {p4.x, p4.y, p4.z, p4.w};
+                constexpr int per = 16 / R::RB;  // rows per 16-byte vector
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    sl[q] = p[q] >> 16;
-                    v[q] = FMT == XCT_F16 ? h16_to_f32(p[q] & 0xffffu) : bf16_to_f32(p[q] & 0xffffu);
+                for (int k = 0; k < per; ++k) {
+                    const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r * per + k), a.swz);
+                    char *dst = smem + slot * R::RB;
+                    if constexpr (R::RB == 8) {
+                        *(u32x2 *)dst = u32x2{u[2 * k], u[2 * k + 1]};
+                    } else if constexpr (R::RB == 4) {
+                        *(uint32_t *)dst = u[k];
+                    } else {
+                        *(uint16_t *)dst = (uint16_t)((k & 1) ? (u[k >> 1] >> 16) : (u[k >> 1] & 0xffffu));
+                    }
                 }
             }
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                float x[F];
-                lds_row<FMT, F>(lds + (int)sl[q] * F, x);
-#pragma unroll
-                for (int f = 0; f < F; ++f) acc[f] = fmaf(v[q], x[f], acc[f]);
+        }
+        __syncthreads();
+        for (int64_t g = g0; g < g1; g += 4) {
+            use_group<FMT, F>(e0, smem, coff, acc);
+            if (g + 4 < g1) e0 = load_group<FMT>(a, (g + 4) * kTileSlots + lane);
+            if (g + 1 < g1) {
+                use_group<FMT, F>(e1, smem, coff, acc);
+                if (g + 5 < g1) e1 = load_group<FMT>(a, (g + 5) * kTileSlots + lane);
+            }
+            if (g + 2 < g1) {
+                use_group<FMT, F>(e2, smem, coff, acc);
+                if (g + 6 < g1) e2 = load_group<FMT>(a, (g + 6) * kTileSlots + lane);
+            }
+            if (g + 3 < g1) {
+                use_group<FMT, F>(e3, smem, coff, acc);
+                if (g + 7 < g1) e3 = load_group<FMT>(a, (g + 7) * kTileSlots + lane);
             }
         }
     }
 
-    const int64_t rt = (int64_t)b * W + wave;
+    // Undo the chunk rotation: slice c*SPC + t of this lane's row is in
+    // accumulator block j = (c - lane) mod CH.
+    float y[F];
+#pragma unroll
+    for (int c = 0; c < R::CH; ++c) {
+#pragma unroll
+        for (int t = 0; t < R::SPC; ++t) {
+            float v = acc[t];
+#pragma unroll
+            for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? acc[j * R::SPC + t] : v;
+            y[c * R::SPC + t] = v;
+        }
+    }
     if (a.scale) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] *= a.scale[f];
+        for (int f = 0; f < F; ++f) y[f] *= a.scale[f];
     }
+    const int64_t rt = (int64_t)b * W + wave;
     if (rt < a.n_row_tiles) {
         float *out = a.yout + (rt * kTileSlots + lane) * F;
         if constexpr (F >= 4) {
 #pragma unroll
-            for (int q = 0; q < F / 4; ++q)
-                ((f32x4 *)out)[q] = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+            for (int q = 0; q < F / 4; ++q) ((f32x4 *)out)[q] = f32x4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
         } else {
 #pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = acc[f];
+            for (int f = 0; f < F; ++f) out[f] = y[f];
         }
     }
     if (a.sq_partial) {
@@ -197,7 +278,7 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
         double *red = (double *)smem;  // [W][F]
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            double q = (double)acc[f] * (double)acc[f];
+            double q = (double)y[f] * (double)y[f];
             for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
             if (lane == 0) red[wave * F + f] = q;
         }
@@ -237,6 +318,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.n_blocks = op.n_blocks;
     a.T = op.T;
     a.remap = L.remap;
+    a.swz = op.swz;
     typedef typename Stor<FMT>::T XT;
     size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
     const size_t red = sizeof(double) * (size_t)op.W * F;

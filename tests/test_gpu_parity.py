@@ -99,6 +99,19 @@ def test_project_backproject_parity(N, M, C, B):
     assert e.max() <= 1e-5, e
 
 
+@pytest.mark.parametrize("opts", [dict(stage_order=1), dict(tile_waves=4, lds_bytes=32768),
+                                  dict(tile_waves=16, xcd_remap=-1), dict(fuse=4)])
+def test_plan_options_keep_parity(opts):
+    N, M, C, B = 64, 90, 64, 5
+    A = gpu_matrix(N, M, C, **opts)
+    Ao, ATo = oracle_mats(N, M, C)
+    x = phantoms.ellipse_batch(N, B, 6, seed=21).float()
+    y = xct.project(A, x.cuda()).cpu()
+    assert rel_err(y.numpy(), oracle.project(Ao, x.double().numpy().reshape(B, -1))).max() <= 1e-5
+    xb = xct.backproject(A, y.cuda()).cpu()
+    assert rel_err(xb.numpy(), oracle.backproject(ATo, y.double().numpy())).max() <= 1e-5
+
+
 def test_output_shape_and_zero_input():
     A = gpu_matrix(37, 23, 41)
     y = xct.project(A, torch.zeros(2, 37, 37, device="cuda"))
