@@ -93,6 +93,12 @@ def main():
     ap.add_argument("--stage-order", type=int, default=0, help="0 sweep (default), 1 Hilbert")
     ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--tile-waves", type=int, default=0)
+    ap.add_argument("--lds-layout", type=int, default=0)
+    ap.add_argument("--lane-order", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (reference for profiler byte counters)")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"],
+                    help="matrix/operand storage of the timed projection step (FP32 is the headline path)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,16 +120,19 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    log(f"building FP32 matrix N={N} M={M} C={C}")
-    opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves)
-    A = xct.Matrix(N, M, C, "f32", **opts)
+    log(f"building {args.dtype} matrix N={N} M={M} C={C}")
+    opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves,
+                lds_layout=args.lds_layout, lane_order=args.lane_order)
+    A = xct.Matrix(N, M, C, args.dtype, **opts)
+    b_a = 6 if args.dtype == "f32" else 4
+    b_x = 4 if args.dtype == "f32" else 2
     info = A.info()
     log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
         f"A^T padded {info['AT']['padded']:,}")
     F = min(16, 1 << max(0, (B - 1).bit_length()))
     nnz = info["A"]["nnz"]
-    bytes_A = alg_bytes(nnz, N * N, M * C, B, F, 6)
-    bytes_AT = alg_bytes(info["AT"]["nnz"], M * C, N * N, B, F, 6)
+    bytes_A = alg_bytes(nnz, N * N, M * C, B, F, b_a)
+    bytes_AT = alg_bytes(info["AT"]["nnz"], M * C, N * N, B, F, b_a)
     bytes_step = bytes_A + bytes_AT
 
     x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device=dev).float()
@@ -134,6 +143,15 @@ def main():
     def step():
         xct.project(A, x, out=y, workspace=ws)
         xct.backproject(A, y, out=xb, workspace=ws)
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read, {nb} bytes written")
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -155,8 +173,9 @@ def main():
     value = bytes_step / (ms_step * 1e-3) / 1e9
     nA, msA = prof["A"]
     nT, msT = prof["AT"]
-    kern_bytes_A = nnz * 6 + F * (N * N + M * C) * 4
-    kern_bytes_AT = info["AT"]["nnz"] * 6 + F * (M * C + N * N) * 4
+    # kernel: matrix entries + staged operand (storage dtype) in + FP32 sums out
+    kern_bytes_A = nnz * b_a + F * (N * N * b_x + M * C * 4)
+    kern_bytes_AT = info["AT"]["nnz"] * b_a + F * (M * C * b_x + N * N * 4)
     launches = nA + nT
     avg_ms = (msA + msT) / max(launches, 1)
     achieved = (kern_bytes_A * nA + kern_bytes_AT * nT) / ((msA + msT) * 1e-3) / 1e9
@@ -174,10 +193,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": f"{B} slices {N}x{N}, {M} angles over [0,pi), {C} channels, shared Siddon "
-                               f"matrix (FP32 values, 16-bit stage-local indices); 40-ellipsoid phantom",
+                               f"matrix ({args.dtype} values, 16-bit stage-local indices); 40-ellipsoid phantom",
                    "n": N, "angles": M, "channels": C, "batch": B, "fuse": F},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "slice_nnz_per_s": (nnz + info["AT"]["nnz"]) * B / (ms_step * 1e-3),
@@ -191,7 +210,7 @@ def main():
                  "staged_slots_AT": info["AT"]["staged_slots"], "stage_order": args.stage_order},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmm<f32,16> (A and A^T launches)",
+            "kernel": f"k_spmm<{args.dtype},{F}> (A and A^T launches)",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -223,11 +242,14 @@ def main():
             return best
 
         log("CGLS FP32")
-        t32 = (cgls_time(A, it) - cgls_time(A, 0)) / it
-        del A
+        A32 = A if args.dtype == "f32" else xct.Matrix(N, M, C, "f32", **opts)
+        t32 = (cgls_time(A32, it) - cgls_time(A32, 0)) / it
+        del A32
+        if args.dtype == "f32":
+            del A
         torch.cuda.empty_cache()
         log("building FP16 matrix")
-        A16 = xct.Matrix(N, M, C, "f16", **opts)
+        A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts)
         log("CGLS FP16 storage")
         t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),

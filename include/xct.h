@@ -79,6 +79,10 @@ typedef struct {
                         0 (default) sweep: for A, by distance along the workgroup's mean ray
                           direction; for A^T, angle-major;
                         1 Hilbert: along the pseudo-Hilbert curve of the input tiles */
+    int lds_layout;  /* tuning: placement of staged rows in LDS against bank conflicts;
+                        0 default (two-term XOR), 1 plain, 2 three-term XOR, 3 one-term XOR */
+    int lane_order;  /* tuning: assignment of a tile's 64 rows to the lanes of a wavefront;
+                        0 default (row-major), 1 transposed */
 } xct_build_opts;
 
 /* Statistics of one operator (A or A^T). */

@@ -141,11 +141,13 @@ struct ProjRows {
     const int32_t *row_coord;  // sinogram rank -> raster tile
     int rowTW;                 // sinogram tiles per tile row
     int inTW;                  // voxel tiles per tile row
+    int lanes;                 // lane_slot order
     template <class V>
     __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
-        const int k = (coord / rowTW) * kTile + (lane >> 3);
-        const int c = (coord % rowTW) * kTile + (lane & 7);
+        const int o = lane_slot(lane, lanes);
+        const int k = (coord / rowTW) * kTile + (o >> 3);
+        const int c = (coord % rowTW) * kTile + (o & 7);
         if (k >= M || c >= C) return;
         trace_ray(N, M, C, k, c, [&](int i, int j, double len) {
             v(key_of[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
@@ -159,11 +161,13 @@ struct BackRows {
     const int32_t *row_coord;  // voxel rank -> raster tile
     int rowTW;
     int inTW;                  // sinogram tiles per tile row
+    int lanes;                 // lane_slot order
     template <class V>
     __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
-        const int i = (coord / rowTW) * kTile + (lane >> 3);
-        const int j = (coord % rowTW) * kTile + (lane & 7);
+        const int o = lane_slot(lane, lanes);
+        const int i = (coord / rowTW) * kTile + (o >> 3);
+        const int j = (coord % rowTW) * kTile + (o & 7);
         if (i >= N || j >= N) return;
         trace_voxel(N, M, C, i, j, [&](int k, int c, double len) {
             v(key_of[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
@@ -373,7 +377,7 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
                     return;
                 }
                 const int n = L.cnt[sl * nthr + tid]++;
-                const int64_t gs = (int64_t)(blk_stage[b] + st) * W + wave;
+                const int64_t gs = (int64_t)blk_stage[b] * W + (int64_t)wave * nst + st;
                 const int64_t g = slab[gs] + n / kGroup;
                 if (g >= slab[gs + 1]) {
                     atomicOr(err, 1);
@@ -540,6 +544,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
                     int W, int T, int swz, xct_dtype vdt, hipStream_t st) {
     op.which = std::is_same<Rows, BackRows>::value ? 1 : 0;
     op.swz = swz;
+    op.lanes = rows.lanes;
     op.n_row_tiles = n_row_tiles;
     op.n_in_tiles = n_in_tiles;
     op.W = W;
@@ -603,13 +608,28 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     std::vector<int32_t> len(nlen);
     if (nlen) XCT_HIP_TRY(hipMemcpyAsync(len.data(), d_len.p, sizeof(int32_t) * nlen, hipMemcpyDeviceToHost, st));
     XCT_HIP_TRY(hipStreamSynchronize(st));
+    // Slabs are laid out wave by wave within a block, each wave's stages in
+    // order, so a wave's entries form one contiguous stream:
+    // slab[blk_stage[b]*W + w*nst_b + s] is the first group of (stage s, wave w).
     std::vector<int64_t> slab(nlen + 1, 0);
-    for (int64_t q = 0; q < nlen; ++q) slab[q + 1] = slab[q] + len[q];
+    {
+        int64_t acc = 0;
+        for (int b = 0; b < nb; ++b) {
+            const int sb = blk_stage[b], nst = blk_stage[b + 1] - blk_stage[b];
+            for (int w = 0; w < W; ++w)
+                for (int sl = 0; sl < nst; ++sl) {
+                    slab[(int64_t)sb * W + (int64_t)w * nst + sl] = acc;
+                    acc += len[(int64_t)(sb + sl) * W + w];
+                }
+        }
+        slab[nlen] = acc;
+    }
     op.n_groups = slab[nlen];
     op.padded = op.n_groups * kTileSlots * kGroup;
     rc = upload(&op.slab, slab);
     if (rc) return rc;
-    const size_t nent = (size_t)std::max<int64_t>(1, op.padded);
+    // at least one group: the kernel's prefetch may re-read group 0
+    const size_t nent = (size_t)std::max<int64_t>(1, op.n_groups) * kTileSlots * kGroup;
     if (vdt == XCT_F32) {
         XCT_HIP_TRY(hipMalloc((void **)&op.slot, sizeof(uint16_t) * nent));
         XCT_HIP_TRY(hipMalloc((void **)&op.val, sizeof(float) * nent));
@@ -688,7 +708,11 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (lds < per_tile || lds > lds_max) return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
     int T = lds / per_tile;
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
-    const int swz = lds_swizzle_bits(F * elem_bytes(value_dtype));
+    if (o.lds_layout < 0 || o.lds_layout > 3) return fail(XCT_ERR_INVALID, "lds_layout must be in [0, 3]");
+    if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
+    static const int kLayoutMode[4] = {1, 0, 2, 3};  // option value -> lds_swizzle variant
+    const int swz = lds_swizzle_bits(F * elem_bytes(value_dtype)) | (kLayoutMode[o.lds_layout] << 8);
+    const int lanes = o.lane_order;
     auto t0 = std::chrono::steady_clock::now();
     xct_matrix *m = new xct_matrix();
     m->n = n;
@@ -701,7 +725,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     int rc = make_grid(m->vol, n, n);
     if (!rc) rc = make_grid(m->sino, n_angles, n_channels);
     if (!rc) {
-        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.TW};
+        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.TW, lanes};
         HostOrder ho;
         const int nb = (int)((m->sino.n_tiles + W - 1) / W);
         if (o.stage_order == 1)
@@ -713,7 +737,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         if (!rc) rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, swz, value_dtype, st);
     }
     if (!rc) {
-        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW};
+        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW, lanes};
         HostOrder ho;
         if (o.stage_order == 1)
             order_hilbert(m->sino, ho);
@@ -815,9 +839,11 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
             const int sl = s - blk_stage[b];
             const int q0 = blk_tile[b] + sl * T;
             const int nt = std::min(T, blk_tile[b + 1] - q0);
+            const int nst = blk_stage[b + 1] - blk_stage[b];
             for (int w = 0; w < W; ++w) {
                 const int64_t rt = (int64_t)b * W + w;
-                for (int64_t g = slab[(int64_t)s * W + w]; g < slab[(int64_t)s * W + w + 1]; ++g) {
+                const int64_t p = (int64_t)blk_stage[b] * W + (int64_t)w * nst + sl;
+                for (int64_t g = slab[p]; g < slab[p + 1]; ++g) {
                     for (int lane = 0; lane < kTileSlots; ++lane) {
                         for (int q = 0; q < kGroup; ++q) {
                             const int64_t idx = (g * kTileSlots + lane) * kGroup + q;
@@ -844,8 +870,9 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
                             const int pos = (int)(logical / kTileSlots), off = (int)(logical % kTileSlots);
                             if (pos >= nt) return fail(XCT_ERR_INTERNAL, "slot outside its stage");
                             const int rco = rcoord[rt];
-                            const int r_row = (rco / rg.TW) * kTile + (lane >> 3);
-                            const int r_col = (rco % rg.TW) * kTile + (lane & 7);
+                            const int ro = lane_slot(lane, op.lanes);
+                            const int r_row = (rco / rg.TW) * kTile + (ro >> 3);
+                            const int r_col = (rco % rg.TW) * kTile + (ro & 7);
                             const int ico = icoord[tile_list[q0 + pos]];
                             const int i_row = (ico / ig.TW) * kTile + (off >> 3);
                             const int i_col = (ico % ig.TW) * kTile + (off & 7);

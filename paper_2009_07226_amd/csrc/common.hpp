@@ -24,12 +24,15 @@ constexpr int kGroup = 4;
 //
 // Output rows are grouped in tiles of 64 (one wavefront); W consecutive row
 // tiles in Hilbert order make one workgroup ("block").  The input tiles a
-// block touches, in Hilbert order, form its tile list; the list is cut into
-// stages of at most T tiles, each loaded into LDS in turn.  For stage s and
-// wave w the entries of the wave's 64 rows that fall in the stage form one
-// ELL slab of slab[s*W+w+1]-slab[s*W+w] groups; entry (group g, lane l,
-// step q) lives at index (g*64 + l)*kGroup + q and holds the stage-local
-// slot (tile position in stage * 64 + offset in tile) and the length.
+// block touches, in its staging order, form its tile list; the list is cut
+// into stages of at most T tiles, each loaded into LDS in turn.  For stage s
+// and wave w the entries of the wave's 64 rows that fall in the stage form
+// one ELL slab; slabs are stored wave by wave (each wave's stages in order),
+// so slab[blk_stage[b]*W + w*nst_b + s] .. [+1] bounds the groups of (s, w)
+// in block b (nst_b stages) and a wave's slabs are one contiguous stream.
+// Entry (group g, lane l, step q) lives at index (g*64 + l)*kGroup + q and
+// holds the stage-local slot (tile position * 64 + offset in tile, placed by
+// lds_swizzle) and the length.
 struct OpPlan {
     int which = 0;  // 0: A (projection), 1: A^T (backprojection)
     int64_t n_row_tiles = 0;
@@ -37,14 +40,15 @@ struct OpPlan {
     int W = 0;  // row tiles (wavefronts) per block
     int T = 0;  // input tiles per stage
     int n_blocks = 0;
-    int swz = 0;  // lds_swizzle bits used for the stored slots
+    int swz = 0;    // lds_swizzle parameter used for the stored slots
+    int lanes = 0;  // lane_slot order of the rows within a row tile
     int64_t n_stages = 0;
     int64_t n_groups = 0;
     int64_t n_list = 0;
     int32_t *blk_stage = nullptr;  // [n_blocks+1]
     int32_t *blk_tile = nullptr;   // [n_blocks+1]
     int32_t *tile_list = nullptr;  // [n_list] input tile ranks
-    int64_t *slab = nullptr;       // [n_stages*W+1] group offsets
+    int64_t *slab = nullptr;       // [n_stages*W+1] group offsets, wave-major within a block
     uint16_t *slot = nullptr;      // F32 format, [n_groups*64*kGroup]
     float *val = nullptr;          // F32 format, [n_groups*64*kGroup]
     uint32_t *packed = nullptr;    // F16/BF16 format: slot << 16 | value bits
@@ -59,10 +63,21 @@ struct OpPlan {
 // both cases over the banks.  Entries store the placed (physical) slot.  The
 // map XORs the low k bits with a function of higher bits it leaves unchanged,
 // so it is its own inverse.
-__host__ __device__ inline uint32_t lds_swizzle(uint32_t s, int k) {
-    if (k <= 0) return s;
+// swz packs k (low 8 bits) and a variant (bits 8..15): 0 plain placement,
+// 1 (default) the two-term XOR above, 2 a three-term XOR (bits k.., 2k..,
+// 3k..), 3 a one-term XOR (bits k.. only).
+__host__ __device__ inline uint32_t lds_swizzle(uint32_t s, int swz) {
+    const int k = swz & 0xff, mode = (swz >> 8) & 0xff;
+    if (k <= 0 || mode == 0) return s;
     const uint32_t m = (1u << k) - 1u;
-    return s ^ ((s >> k) & m) ^ ((s >> (2 * k)) & m);
+    uint32_t x = s ^ ((s >> k) & m);
+    if (mode != 3) x ^= (s >> (2 * k)) & m;
+    if (mode == 2) x ^= (s >> (3 * k)) & m;
+    return x;
+}
+// Lane -> slot of the row tile: 0 row-major (lane = slot), 1 transposed.
+__host__ __device__ inline int lane_slot(int lane, int order) {
+    return order ? (((lane & 7) << 3) | (lane >> 3)) : lane;
 }
 // k for rows of row_bytes bytes (0 when a row fills a line or is below 16 B).
 inline int lds_swizzle_bits(int row_bytes) {

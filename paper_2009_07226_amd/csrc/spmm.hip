@@ -100,7 +100,7 @@ struct SpmmArgs {
     const float *scale;
     double *sq_partial;
     int64_t n_row_tiles;
-    int n_blocks, T, remap, swz;
+    int n_blocks, T, remap, swz, lanes;
 };
 
 // One group: kGroup consecutive ELL steps of one lane.
@@ -162,12 +162,19 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const char *lds, 
     }
 }
 
+// Entries in flight per wavefront: the ring holds the next kRing groups of
+// the wave's entry stream, which runs through all stages of the block.
+template <int FMT> struct RingDepth { static constexpr int value = 6; };
+template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
+
 template <int FMT, int F>
 __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     typedef RowShape<FMT, F> R;
+    constexpr int D = RingDepth<FMT>::value;
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6;
-    const int wave = tid >> 6, lane = tid & 63;
+    // wave-uniform: keeps the slab bounds and loop control in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     int b = blockIdx.x;
     if (a.remap) {
         const int per = (a.n_blocks + 7) >> 3;
@@ -189,26 +196,66 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     const int s0 = a.blk_stage[b], s1 = a.blk_stage[b + 1];
     const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
     const u32x4 *xin = (const u32x4 *)a.xin;
+
+    // The wave's entries are one contiguous stream of groups [gw, ge);
+    // stage s uses slab[p0 + s - s0] .. slab[p0 + s - s0 + 1].
+    const int nst = s1 - s0;
+    const int64_t p0 = (int64_t)s0 * W + (int64_t)wave * nst;
+    const int64_t gw = a.slab[p0], ge = a.slab[p0 + nst];
+    int64_t lg = gw;  // next group to load
+    // Slot d of the ring holds group sg[d].  Every visit of a slot reloads it
+    // unconditionally (a slot that was not consumed reloads the group it
+    // already holds; past the end of the stream the last group is re-read),
+    // so each ring register is only ever the direct target of its own load:
+    // no register copies and no waits beyond the oldest load.
+    // (group 0 always exists: the builder allocates at least one group)
+    auto take = [&]() -> int64_t {
+        const int64_t g = lg < ge ? lg : (ge > 0 ? ge - 1 : 0);
+        ++lg;
+        return g;
+    };
+    Group<FMT> e[D];
+    int64_t sg[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        sg[d] = take();
+        e[d] = load_group<FMT>(a, sg[d] * kTileSlots + lane);
+    }
+    int ph = 0;  // ring slot holding the next group
     for (int s = s0; s < s1; ++s) {
         const int q0 = t0 + (s - s0) * a.T;
         const int nt = min(a.T, t1 - q0);
-        const int64_t g0 = a.slab[(int64_t)s * W + wave], g1 = a.slab[(int64_t)s * W + wave + 1];
-        // The first groups of this stage are requested before the staging
-        // round so their latency overlaps it; afterwards each consumed group
-        // is replaced by the one four places ahead.
-        Group<FMT> e0, e1, e2, e3;
-        if (g0 < g1) e0 = load_group<FMT>(a, g0 * kTileSlots + lane);
-        if (g0 + 1 < g1) e1 = load_group<FMT>(a, (g0 + 1) * kTileSlots + lane);
-        if (g0 + 2 < g1) e2 = load_group<FMT>(a, (g0 + 2) * kTileSlots + lane);
-        if (g0 + 3 < g1) e3 = load_group<FMT>(a, (g0 + 3) * kTileSlots + lane);
+        const int n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
         __syncthreads();  // previous stage fully consumed
-        for (int e = tid; e < nt * kVecPerTile; e += nthr) {
-            const int q = e / kVecPerTile, r = e % kVecPerTile;
-            const u32x4 v = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + r];
-            if constexpr (R::RB >= 16) {
-                const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
-                ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v;
-            } else {
+        if constexpr (R::RB >= 16) {
+            // A tile is a multiple of 64 vectors, so the tile of each copied
+            // vector is wave-uniform: its index comes through a scalar load.
+            // The vector loads of a batch are all issued before their stores.
+            constexpr int kBatch = 8;
+            const int total = nt * kVecPerTile;
+            for (int base = 0; base < total; base += kBatch * nthr) {
+                u32x4 v[kBatch];
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int e2 = base + k * nthr + tid;
+                    const int q = __builtin_amdgcn_readfirstlane(min(e2, total - 1) / kVecPerTile);
+                    const int r = min(e2, total - 1) % kVecPerTile;
+                    v[k] = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + r];
+                }
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int e2 = base + k * nthr + tid;
+                    if (e2 < total) {
+                        const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
+                        const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
+                        ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v[k];
+                    }
+                }
+            }
+        } else {
+            for (int e2 = tid; e2 < nt * kVecPerTile; e2 += nthr) {
+                const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
+                const u32x4 v = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + r];
                 constexpr int per = 16 / R::RB;  // rows per 16-byte vector
                 const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -226,22 +273,21 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
             }
         }
         __syncthreads();
-        for (int64_t g = g0; g < g1; g += 4) {
-            use_group<FMT, F>(e0, smem, coff, acc);
-            if (g + 4 < g1) e0 = load_group<FMT>(a, (g + 4) * kTileSlots + lane);
-            if (g + 1 < g1) {
-                use_group<FMT, F>(e1, smem, coff, acc);
-                if (g + 5 < g1) e1 = load_group<FMT>(a, (g + 5) * kTileSlots + lane);
-            }
-            if (g + 2 < g1) {
-                use_group<FMT, F>(e2, smem, coff, acc);
-                if (g + 6 < g1) e2 = load_group<FMT>(a, (g + 6) * kTileSlots + lane);
-            }
-            if (g + 3 < g1) {
-                use_group<FMT, F>(e3, smem, coff, acc);
-                if (g + 7 < g1) e3 = load_group<FMT>(a, (g + 7) * kTileSlots + lane);
+        // consume this stage's n groups, the first one in slot ph; every
+        // consumed slot is refilled from the cursor, possibly with a later
+        // stage's group
+        for (int i = -ph; i < n; i += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int k = i + d;
+                if (k >= 0 && k < n) {
+                    use_group<FMT, F>(e[d], smem, coff, acc);
+                    sg[d] = take();
+                }
+                e[d] = load_group<FMT>(a, sg[d] * kTileSlots + lane);
             }
         }
+        ph = (ph + n) % D;
     }
 
     // Undo the chunk rotation: slice c*SPC + t of this lane's row is in
@@ -263,7 +309,7 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     }
     const int64_t rt = (int64_t)b * W + wave;
     if (rt < a.n_row_tiles) {
-        float *out = a.yout + (rt * kTileSlots + lane) * F;
+        float *out = a.yout + (rt * kTileSlots + lane_slot(lane, a.lanes)) * F;
         if constexpr (F >= 4) {
 #pragma unroll
             for (int q = 0; q < F / 4; ++q) ((f32x4 *)out)[q] = f32x4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
@@ -319,6 +365,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.T = op.T;
     a.remap = L.remap;
     a.swz = op.swz;
+    a.lanes = op.lanes;
     typedef typename Stor<FMT>::T XT;
     size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
     const size_t red = sizeof(double) * (size_t)op.W * F;
