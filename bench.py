@@ -39,6 +39,23 @@ def alg_bytes(nnz, n_in, n_out, B, F, b_a, b_vec=4):
     return math.ceil(B / F) * nnz * b_a + B * (n_in + n_out) * b_vec
 
 
+def measured_traffic(dtype, N, M, B, default_opts):
+    """HBM bytes per SpMM launch from the committed rocprofv3 counter summary of
+    this workload, if it was taken on the current kernel sources; else None."""
+    from paper_2009_07226_amd import pmc_summary
+    path = os.path.join(ROOT, "profiles", f"k_spmm_traffic_{dtype}_{B}x{N}x{M}.json")
+    if not default_opts or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != pmc_summary.kernel_sources_sha():
+        return None
+    ks = list(rec["kernels"].values())
+    n = sum(k["launches"] for k in ks)
+    tot = sum((k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]) * k["launches"] for k in ks)
+    return tot / n if n else None
+
+
 def cpu_baseline(N, M, C, B, x_host, bytes_step, budget_s):
     """FP64 oracle (matrix-free sampled rows of A and voxels of A^T) on the host cores."""
     import numpy as np
@@ -215,7 +232,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.dtype, N, M, B,
+                                        not (args.stage_order or args.lds_bytes or args.tile_waves or
+                                             args.lds_layout or args.lane_order)),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": {"A": kern_bytes_A, "AT": kern_bytes_AT},
             "launch_ms": {"A": round(msA / max(nA, 1), 4), "AT": round(msT / max(nT, 1), 4)},
@@ -252,6 +272,31 @@ def main():
         A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts)
         log("CGLS FP16 storage")
         t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
+        # the FP16 operators' projection + backprojection step, for reference
+        i16 = A16.info()
+        ws16 = A16.spmm_workspace(B)
+        for _ in range(2):
+            xct.project(A16, x, out=y, workspace=ws16)
+        torch.cuda.synchronize()
+        xct.profile_enable(True)
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        for _ in range(args.steps):
+            xct.project(A16, x, out=y, workspace=ws16)
+            xct.backproject(A16, y, out=xb, workspace=ws16)
+        f1.record()
+        torch.cuda.synchronize()
+        xct.profile_enable(False)
+        p16 = xct.profile_read()
+        ms16 = f0.elapsed_time(f1) / args.steps
+        kb16 = {w: i16[w]["nnz"] * 4 + F * (N * N * 2 + M * C * 4) for w in ("A", "AT")}
+        ach16 = (kb16["A"] * p16["A"][0] + kb16["AT"] * p16["AT"][0]) / ((p16["A"][1] + p16["AT"][1]) * 1e-3) / 1e9
+        b16 = alg_bytes(i16["A"]["nnz"], N * N, M * C, B, F, 4) + alg_bytes(i16["AT"]["nnz"], M * C, N * N, B, F, 4)
+        out["fp16_step"] = {"ms_per_step": round(ms16, 4), "GBps": round(b16 / (ms16 * 1e-3) / 1e9, 2),
+                            "kernel_GBps": round(ach16, 2), "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4),
+                            "launch_ms": {"A": round(p16["A"][1] / max(p16["A"][0], 1), 4),
+                                          "AT": round(p16["AT"][1] / max(p16["AT"][0], 1), 4)},
+                            "padded_A": i16["A"]["padded"], "padded_AT": i16["AT"]["padded"]}
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),
                        "fp16_speedup": round(t32 / t16, 3),
                        "build_s_f16": round(A16.info()["build_seconds"], 3)}

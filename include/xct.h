@@ -69,10 +69,11 @@ enum {
 
 /* Build options; zero in any field selects the default. */
 typedef struct {
-    int tile_waves; /* row tiles (64 rows each, one wavefront) per workgroup; default 8, max 16 */
+    int tile_waves; /* row tiles (64 rows each, one wavefront) per workgroup; default 16, max 16 */
     int fuse;       /* largest number of slices fused per matrix pass (F); 1,2,4,8 or 16; default 16 */
-    int lds_bytes;  /* LDS bytes per workgroup for one stage of staged input at F = fuse;
-                       default 81920 (two workgroups per CU) */
+    int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input (plus
+                       256 bytes of counters for FP16/BF16 matrices); default: all of the
+                       device's LDS per workgroup (160 KiB on gfx950) */
     int xcd_remap;  /* 1 (default): consecutive workgroups of the Hilbert order run on the
                        same XCD; -1: plain order */
     int stage_order; /* order in which a workgroup stages its input tiles:

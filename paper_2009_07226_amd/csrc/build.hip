@@ -386,8 +386,9 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
                 const int64_t idx = (g * kTileSlots + lane) * kGroup + (n % kGroup);
                 const uint32_t s = lds_swizzle((uint32_t)((pos % T) * kTileSlots + off), swz);
                 if (FMT == XCT_F32) {
-                    slot[idx] = (uint16_t)s;
-                    val[idx] = (float)len;
+                    const int64_t li = (int64_t)lane * kGroup + (n % kGroup);
+                    slot[g * 768 + li] = (uint16_t)s;
+                    val[g * 384 + 128 + li] = (float)len;
                 } else if (FMT == XCT_F16) {
                     packed[idx] = (s << 16) | dbl_to_half_bits(len);
                 } else {
@@ -533,7 +534,7 @@ static int upload_order(const HostOrder &h, int64_t n_in, DevOrder &d) {
 }
 
 static void free_op(OpPlan &op) {
-    void *ps[] = {op.blk_stage, op.blk_tile, op.tile_list, op.slab, op.slot, op.val, op.packed};
+    void *ps[] = {op.blk_stage, op.blk_tile, op.tile_list, op.slab, op.ent};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     op = OpPlan();
@@ -630,14 +631,14 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     if (rc) return rc;
     // at least one group: the kernel's prefetch may re-read group 0
     const size_t nent = (size_t)std::max<int64_t>(1, op.n_groups) * kTileSlots * kGroup;
+    const size_t ent_bytes = nent * (vdt == XCT_F32 ? 6 : 4);
+    XCT_HIP_TRY(hipMalloc(&op.ent, ent_bytes));
+    XCT_HIP_TRY(hipMemsetAsync(op.ent, 0, ent_bytes, st));
     if (vdt == XCT_F32) {
-        XCT_HIP_TRY(hipMalloc((void **)&op.slot, sizeof(uint16_t) * nent));
-        XCT_HIP_TRY(hipMalloc((void **)&op.val, sizeof(float) * nent));
-        XCT_HIP_TRY(hipMemsetAsync(op.slot, 0, sizeof(uint16_t) * nent, st));
-        XCT_HIP_TRY(hipMemsetAsync(op.val, 0, sizeof(float) * nent, st));
+        op.slot = (uint16_t *)op.ent;
+        op.val = (float *)op.ent;
     } else {
-        XCT_HIP_TRY(hipMalloc((void **)&op.packed, sizeof(uint32_t) * nent));
-        XCT_HIP_TRY(hipMemsetAsync(op.packed, 0, sizeof(uint32_t) * nent, st));
+        op.packed = (uint32_t *)op.ent;
     }
     auto fill = [&](auto kern) -> int {
         XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -692,7 +693,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         return fail(XCT_ERR_INVALID, "stage_order must be 0 (sweep) or 1 (Hilbert)");
     xct_build_opts o = {};
     if (opts) o = *opts;
-    const int W = o.tile_waves ? o.tile_waves : 8;
+    const int W = o.tile_waves ? o.tile_waves : 16;
     const int F = o.fuse ? o.fuse : 16;
     int lds = o.lds_bytes;
     if (W < 1 || W > 16) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16]");
@@ -704,9 +705,11 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     int lds_max = 0;
     he = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (he != hipSuccess) return fail(XCT_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
-    if (!lds) lds = std::min(81920, lds_max);
-    if (lds < per_tile || lds > lds_max) return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
-    int T = lds / per_tile;
+    if (!lds) lds = lds_max;  // one workgroup of 16 waves per CU with the whole LDS
+    const int reserve = lds_reserve(value_dtype);
+    if (lds < per_tile + reserve || lds > lds_max)
+        return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
+    int T = (lds - reserve) / per_tile;
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
     if (o.lds_layout < 0 || o.lds_layout > 3) return fail(XCT_ERR_INVALID, "lds_layout must be in [0, 3]");
     if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
@@ -826,8 +829,8 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
     if (!rc) rc = download(rcoord, rg.coord_of, rg.n_tiles);
     if (!rc) rc = download(icoord, ig.coord_of, ig.n_tiles);
     if (!rc && m->vdt == XCT_F32) {
-        rc = download(slot, op.slot, op.padded);
-        if (!rc) rc = download(val, op.val, op.padded);
+        rc = download(slot, op.slot, op.padded * 3);  // the whole buffer, 6 B per entry
+        if (!rc) val.assign((float *)slot.data(), (float *)slot.data() + op.padded * 3 / 2);
     } else if (!rc) {
         rc = download(packed, op.packed, op.padded);
     }
@@ -850,8 +853,9 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
                             uint32_t sidx;
                             float v;
                             if (m->vdt == XCT_F32) {
-                                sidx = slot[idx];
-                                v = val[idx];
+                                const int64_t li = (int64_t)lane * kGroup + q;
+                                sidx = slot[g * 768 + li];
+                                v = val[g * 384 + 128 + li];
                             } else {
                                 sidx = packed[idx] >> 16;
                                 const uint16_t bits = (uint16_t)(packed[idx] & 0xffff);

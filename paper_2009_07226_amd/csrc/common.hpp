@@ -19,6 +19,9 @@ constexpr int kTileSlots = 64;
 // ELL entries are stored in groups of kGroup consecutive steps per lane so
 // one lane reads a group with a single wide load.
 constexpr int kGroup = 4;
+// LDS bytes reserved after the staged rows (the SpMM's claim counters,
+// used with 16-bit operands).
+constexpr int lds_reserve(int value_dtype) { return value_dtype == XCT_F32 ? 0 : 256; }
 
 // One operator (A or A^T) in staged-ELL form.
 //
@@ -49,9 +52,17 @@ struct OpPlan {
     int32_t *blk_tile = nullptr;   // [n_blocks+1]
     int32_t *tile_list = nullptr;  // [n_list] input tile ranks
     int64_t *slab = nullptr;       // [n_stages*W+1] group offsets, wave-major within a block
-    uint16_t *slot = nullptr;      // F32 format, [n_groups*64*kGroup]
-    float *val = nullptr;          // F32 format, [n_groups*64*kGroup]
-    uint32_t *packed = nullptr;    // F16/BF16 format: slot << 16 | value bits
+    // Entries, one buffer (ent) holding n_groups groups:
+    //  F32 format: a group is 1536 bytes, 64 lanes x 4 u16 slots (512 B) then
+    //    64 lanes x 4 f32 lengths (1 KB); slot of (g, lane, q) is
+    //    slot[g*768 + lane*4 + q], its length val[g*384 + 128 + lane*4 + q];
+    //  F16/BF16 format: a group is 1024 bytes, packed[(g*64 + lane)*4 + q] =
+    //    slot << 16 | value bits.
+    // slot, val and packed are views of ent.
+    void *ent = nullptr;
+    uint16_t *slot = nullptr;
+    float *val = nullptr;
+    uint32_t *packed = nullptr;
     int64_t nnz = 0, padded = 0, staged_slots = 0, bytes = 0;
 };
 

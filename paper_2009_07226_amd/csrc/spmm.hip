@@ -109,14 +109,15 @@ template <> struct Group<XCT_F32> { u32x2 s; f32x4 v; };
 template <> struct Group<XCT_F16> { u32x4 p; };
 template <> struct Group<XCT_BF16> { u32x4 p; };
 
+// Group gi of lane `lane` (entry layout: see OpPlan).
 template <int FMT>
-__device__ __forceinline__ Group<FMT> load_group(const SpmmArgs &a, int64_t e) {
+__device__ __forceinline__ Group<FMT> load_group(const SpmmArgs &a, int64_t gi, int lane) {
     Group<FMT> g;
     if constexpr (FMT == XCT_F32) {
-        g.s = __builtin_nontemporal_load((const u32x2 *)a.slot + e);
-        g.v = __builtin_nontemporal_load((const f32x4 *)a.val + e);
+        g.s = __builtin_nontemporal_load((const u32x2 *)a.slot + gi * 192 + lane);
+        g.v = __builtin_nontemporal_load((const f32x4 *)a.val + gi * 96 + 32 + lane);
     } else {
-        g.p = __builtin_nontemporal_load((const u32x4 *)a.packed + e);
+        g.p = __builtin_nontemporal_load((const u32x4 *)a.packed + gi * kTileSlots + lane);
     }
     return g;
 }
@@ -219,28 +220,27 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         sg[d] = take();
-        e[d] = load_group<FMT>(a, sg[d] * kTileSlots + lane);
+        e[d] = load_group<FMT>(a, sg[d], lane);
     }
     int ph = 0;  // ring slot holding the next group
-    for (int s = s0; s < s1; ++s) {
-        const int q0 = t0 + (s - s0) * a.T;
-        const int nt = min(a.T, t1 - q0);
-        const int n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
-        __syncthreads();  // previous stage fully consumed
+
+    // Copy of one stage into LDS.  Vector c (16 bytes) of a stage that starts
+    // at tile-list position q0 comes from tile tile_list[q0 + c / kVecPerTile]
+    // and goes to the placed row of its slot.
+    auto copy_static = [&](int q0, int nt) {
         if constexpr (R::RB >= 16) {
             // A tile is a multiple of 64 vectors, so the tile of each copied
-            // vector is wave-uniform: its index comes through a scalar load.
-            // The vector loads of a batch are all issued before their stores.
-            constexpr int kBatch = 8;
+            // vector is wave-uniform (a scalar load); all loads of a batch are
+            // issued before their stores.
+            constexpr int kBatch = 10;
             const int total = nt * kVecPerTile;
             for (int base = 0; base < total; base += kBatch * nthr) {
                 u32x4 v[kBatch];
 #pragma unroll
                 for (int k = 0; k < kBatch; ++k) {
-                    const int e2 = base + k * nthr + tid;
-                    const int q = __builtin_amdgcn_readfirstlane(min(e2, total - 1) / kVecPerTile);
-                    const int r = min(e2, total - 1) % kVecPerTile;
-                    v[k] = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + r];
+                    const int e2 = min(base + k * nthr + tid, total - 1);
+                    const int q = __builtin_amdgcn_readfirstlane(e2 / kVecPerTile);
+                    v[k] = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + e2 % kVecPerTile];
                 }
 #pragma unroll
                 for (int k = 0; k < kBatch; ++k) {
@@ -272,7 +272,24 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
                 }
             }
         }
-        __syncthreads();
+    };
+
+    // 16-bit operands: the next stage's copy is claimed chunk by chunk by
+    // the waves that finish first (below); two claim counters follow the
+    // stage buffer, one per stage parity.  FP32 rows make the stage loop
+    // bound by LDS bandwidth, where early loads gain nothing, so FP32 keeps
+    // the plain copy between two barriers.
+    constexpr bool kClaimed = FMT != XCT_F32 && R::RB >= 16;
+    int *claim = (int *)(smem + (size_t)a.T * kTileSlots * R::RB);
+    if (kClaimed && tid == 0) {
+        claim[0] = 0;
+        claim[1] = 0;
+    }
+    if (s0 < s1) copy_static(t0, min(a.T, t1 - t0));
+    __syncthreads();
+
+    for (int s = s0; s < s1; ++s) {
+        const int n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
         // consume this stage's n groups, the first one in slot ph; every
         // consumed slot is refilled from the cursor, possibly with a later
         // stage's group
@@ -284,10 +301,62 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
                     use_group<FMT, F>(e[d], smem, coff, acc);
                     sg[d] = take();
                 }
-                e[d] = load_group<FMT>(a, sg[d] * kTileSlots + lane);
+                e[d] = load_group<FMT>(a, sg[d], lane);
             }
         }
         ph = (ph + n) % D;
+
+        if (s + 1 < s1) {
+            const int q0n = t0 + (s + 1 - s0) * a.T;
+            const int ntn = min(a.T, t1 - q0n);
+            if constexpr (kClaimed) {
+                // The next stage's copy is split in chunks of 64 vectors that
+                // waves claim as they finish this stage: early waves load them
+                // while the slow ones still compute, so the copy leaves the
+                // critical path.  Data is stored once every wave is done.
+                constexpr int kClaim = 12;
+                const int chunks = ntn * kVecPerTile / 64;
+                const int par = (s - s0) & 1;
+                int c0 = 0;
+                if (lane == 0) c0 = atomicAdd(&claim[par], kClaim);
+                c0 = __builtin_amdgcn_readfirstlane(__shfl(c0, 0, 64));
+                const int cn = max(0, min(kClaim, chunks - c0));
+                u32x4 v[kClaim];
+                if (cn > 0) {
+                    // one branch around unconditional loads (a partial claim
+                    // re-reads its last chunk), so the loads stay in flight together
+#pragma unroll
+                    for (int k = 0; k < kClaim; ++k) {
+                        const int c = c0 + min(k, cn - 1);
+                        const int q = c * 64 / kVecPerTile;
+                        v[k] = xin[(int64_t)a.tile_list[q0n + q] * kVecPerTile + (c * 64) % kVecPerTile + lane];
+                    }
+                }
+                __syncthreads();  // every wave is done with this stage's data
+                if (tid == 0) claim[par] = 0;  // reused two stages later
+#pragma unroll
+                for (int k = 0; k < kClaim; ++k) {
+                    if (k < cn) {
+                        const int e2 = (c0 + k) * 64 + lane;
+                        const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
+                        const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
+                        ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v[k];
+                    }
+                }
+                // chunks nobody claimed (only when a stage has more than W*kClaim)
+                for (int c = W * kClaim + wave; c < chunks; c += W) {
+                    const int e2 = c * 64 + lane;
+                    const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
+                    const u32x4 w = xin[(int64_t)a.tile_list[q0n + q] * kVecPerTile + r];
+                    const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
+                    ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = w;
+                }
+            } else {
+                __syncthreads();
+                copy_static(q0n, ntn);
+            }
+            __syncthreads();  // next stage in place
+        }
     }
 
     // Undo the chunk rotation: slice c*SPC + t of this lane's row is in
@@ -367,7 +436,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.swz = op.swz;
     a.lanes = op.lanes;
     typedef typename Stor<FMT>::T XT;
-    size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
+    size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT) + lds_reserve(FMT);
     const size_t red = sizeof(double) * (size_t)op.W * F;
     if (smem < red) smem = red;
     static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far

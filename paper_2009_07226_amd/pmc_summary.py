@@ -1,0 +1,99 @@
+"""Summarise rocprofv3 counter runs of the SpMM kernel into HBM traffic per launch.
+
+Usage (after two rocprofv3 --pmc runs of bench.py with --copy-calibration-mib,
+one collecting FETCH_SIZE and one WRITE_SIZE, each with -f csv):
+
+    python -m paper_2009_07226_amd.pmc_summary FETCH.csv WRITE.csv OUT_PREFIX \
+        --copy-mib 1024 --command "<the rocprofv3 commands>"
+
+FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Their scale on a
+given device is calibrated with the plain device copy of known size that
+bench.py runs (`--copy-calibration-mib`): factor = bytes moved / counter value.
+Writes OUT_PREFIX.md (human-readable) and OUT_PREFIX.json (figures and the
+SHA-256 of the kernel sources they were measured on; bench.py reports the
+traffic only while the sources still match).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/spmm.hip", "csrc/build.hip", "csrc/common.hpp")
+
+
+def kernel_sources_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _read(path, counter):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    by = defaultdict(list)
+    for r in rows:
+        by[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return by
+
+
+def summarise(fetch_csv, write_csv, copy_mib):
+    f = _read(fetch_csv, "FETCH_SIZE")
+    w = _read(write_csv, "WRITE_SIZE")
+    nbytes = copy_mib << 20
+    copy_f = max(v for k, vs in f.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in w.items() if "copyBuffer" in k for v in vs)
+    fscale = nbytes / (copy_f * 1024.0)
+    wscale = nbytes / (copy_w * 1024.0)
+    out = {"copy_bytes": nbytes, "fetch_scale": fscale, "write_scale": wscale, "kernels": {}}
+    for name, vs in f.items():
+        if "k_spmm" not in name:
+            continue
+        ws = w.get(name, [0.0])
+        out["kernels"][name] = {
+            "launches": len(vs),
+            "fetch_bytes_per_launch": sum(vs) / len(vs) * 1024.0 * fscale,
+            "write_bytes_per_launch": sum(ws) / len(ws) * 1024.0 * wscale,
+            "fetch_kib_raw": vs,
+            "write_kib_raw": ws,
+        }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_csv")
+    ap.add_argument("write_csv")
+    ap.add_argument("out_prefix")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--workload", default="")
+    a = ap.parse_args()
+    s = summarise(a.fetch_csv, a.write_csv, a.copy_mib)
+    s["kernel_sources_sha256"] = kernel_sources_sha()
+    s["command"] = a.command
+    s["workload"] = a.workload
+    with open(a.out_prefix + ".json", "w") as fh:
+        json.dump(s, fh, indent=1)
+    lines = [f"# SpMM HBM traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE): {a.workload}", "",
+             "Command:", "", "```", a.command, "```", "",
+             f"Calibration: a plain device copy of {a.copy_mib} MiB reads FETCH_SIZE x {s['fetch_scale']:.4f} "
+             f"and writes WRITE_SIZE x {s['write_scale']:.4f} of its true bytes (factors applied below).", "",
+             "| Kernel | Launches | Read GB / launch | Written GB / launch | raw FETCH_SIZE KiB | raw WRITE_SIZE KiB |",
+             "|---|---|---|---|---|---|"]
+    for name, k in s["kernels"].items():
+        lines.append(f"| {name.split('(')[0]} | {k['launches']} | {k['fetch_bytes_per_launch'] / 1e9:.3f} | "
+                     f"{k['write_bytes_per_launch'] / 1e9:.3f} | {', '.join(f'{v:.6g}' for v in k['fetch_kib_raw'])} | "
+                     f"{', '.join(f'{v:.6g}' for v in k['write_kib_raw'])} |")
+    lines += ["", f"Kernel sources SHA-256: `{s['kernel_sources_sha256']}`"]
+    with open(a.out_prefix + ".md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()
