@@ -80,10 +80,15 @@ typedef struct {
                         0 (default) sweep: for A, by distance along the workgroup's mean ray
                           direction; for A^T, angle-major;
                         1 Hilbert: along the pseudo-Hilbert curve of the input tiles */
-    int lds_layout;  /* tuning: placement of staged rows in LDS against bank conflicts;
-                        0 default (two-term XOR), 1 plain, 2 three-term XOR, 3 one-term XOR */
+    int lds_layout;  /* tuning: placement of staged rows in LDS; 0 default (plain: row = slot;
+                        bank conflicts are handled by the slab schedule), 1 two-term XOR,
+                        2 three-term XOR, 3 one-term XOR of the slot's bit fields */
     int lane_order;  /* tuning: assignment of a tile's 64 rows to the lanes of a wavefront;
                         0 default (row-major), 1 transposed */
+    int slab_order;  /* order of a lane's entries within a (stage, wavefront) slab:
+                        0 (default) scheduled so that the lanes served together by one
+                          16-byte LDS read hit distinct bank groups (rows of 32 or 64 B);
+                        1 ray/voxel tracing order */
 } xct_build_opts;
 
 /* Statistics of one operator (A or A^T). */
@@ -95,6 +100,9 @@ typedef struct {
     int64_t staged_slots; /* input slots loaded over all stages (64 per tile) */
     int32_t blocks;       /* workgroups per pass */
     int32_t tiles_per_stage;
+    int64_t slabs;          /* (stage, wavefront) slabs */
+    int64_t balanced_slabs; /* slabs scheduled against LDS bank conflicts (empty ones included);
+                               equals slabs unless scheduling is off or a slab is too long for it */
 } xct_op_stats;
 
 typedef struct {

@@ -400,6 +400,261 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
     }
 }
 
+// ---- step order of the slabs against LDS bank conflicts --------------------
+//
+// The SpMM reads a staged row of RB bytes as CH = RB / 16 chunks of 16 bytes,
+// lane l taking chunk (j + l) mod CH at sub-step j.  A wavefront's 16-byte
+// LDS read on gfx950 is served in four phases of 16 lanes, lane l being in
+// phase (bit 2 ^ bit 3 ^ bit 4 of l) + 2 * (bit 5 of l), and within a phase
+// each group of four banks (the 16 B at a given offset mod 256 B) delivers
+// one distinct address per cycle (measured with lane/address permutations).
+// Chunk c of placed row r lies in group (r * CH + c) mod 16, so the lanes of
+// one phase that share l mod CH read without conflict when their rows differ
+// mod Q = 16 / CH.  Each such set of Q lanes (a unit) is scheduled step by
+// step: the entries of a lane within a slab may be taken in any order (the
+// sum is the same up to rounding) and its padding steps may point at any row
+// (their length is 0), so at every step the unit's lanes take entries of Q
+// different row classes wherever their remaining entries allow.  Lanes whose
+// remaining entries fill all remaining steps go first, the most constrained
+// of them first; then lanes with the most entries left; the rest pad.
+
+// The quads (4 consecutive lanes) of a 32-lane half in phase parity p.
+__device__ __forceinline__ int phase_quad(int p, int a) {
+    const int q0[4] = {0, 3, 5, 6}, q1[4] = {1, 2, 4, 7};
+    return p ? q1[a] : q0[a];
+}
+
+// LDS bytes per step of a slab and fixed part, for a launch of k_balance.
+inline size_t balance_lds_step(xct_dtype vdt) { return (size_t)kTileSlots * (vdt == XCT_F32 ? 10 : 8); }
+inline size_t balance_lds_fixed(int Q) { return (size_t)2 * kTileSlots * Q * sizeof(uint16_t); }
+
+template <int FMT, int Q>
+__global__ void __launch_bounds__(64) k_balance(const int64_t *slab, int L_cap, uint16_t *slot, float *val,
+                                                uint32_t *packed, unsigned long long *n_done, int *err) {
+    constexpr int CH = 16 / Q;  // chunks per staged row
+    constexpr int NU = 64 / Q;  // units per wavefront
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x;
+    const int64_t g0 = slab[blockIdx.x];
+    const int L = (int)(slab[blockIdx.x + 1] - g0) * kGroup;
+    if (L > L_cap) return;  // whole workgroup; left in tracing order
+    if (L == 0) {
+        if (lane == 0) atomicAdd(n_done, 1ull);
+        return;
+    }
+    char *p = smem;
+    uint32_t *ent = (uint32_t *)p;  // F32: length bits; 16-bit: packed entry
+    p += sizeof(uint32_t) * (size_t)L * 64;
+    uint16_t *eslot = (uint16_t *)p;  // F32 only
+    if (FMT == XCT_F32) p += sizeof(uint16_t) * (size_t)L * 64;
+    uint16_t *order = (uint16_t *)p;  // per lane: its steps sorted by row class
+    p += sizeof(uint16_t) * (size_t)L * 64;
+    uint16_t *src = (uint16_t *)p;  // new step -> old step, or 0x8000 | class for padding
+    p += sizeof(uint16_t) * (size_t)L * 64;
+    uint16_t *nxt = (uint16_t *)p;  // [64][Q] next position in order[] per class
+    p += sizeof(uint16_t) * 64 * Q;
+    uint16_t *lim = (uint16_t *)p;  // [64][Q] end of each class in order[]
+
+    for (int t = 0; t < L; t += kGroup) {
+        const int64_t g = g0 + t / kGroup;
+        if constexpr (FMT == XCT_F32) {
+            const uint16_t *sp = slot + g * 768 + lane * kGroup;
+            const float *vp = val + g * 384 + 128 + lane * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                ent[(t + q) * 64 + lane] = __float_as_uint(vp[q]);
+                eslot[(t + q) * 64 + lane] = sp[q];
+            }
+        } else {
+            const uint32_t *pp = packed + (g * kTileSlots + lane) * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) ent[(t + q) * 64 + lane] = pp[q];
+        }
+    }
+    auto real_cls = [&](int t, int l, int &cls) -> bool {
+        const uint32_t e = ent[t * 64 + l];
+        if constexpr (FMT == XCT_F32) {
+            cls = eslot[t * 64 + l] & (Q - 1);
+            return e != 0u;
+        } else {
+            cls = (int)(e >> 16) & (Q - 1);
+            return (e & 0xffffu) != 0u;
+        }
+    };
+    // counting sort of this lane's steps by class
+    {
+        int c[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) c[q] = 0;
+        for (int t = 0; t < L; ++t) {
+            int cls;
+            const bool r = real_cls(t, lane, cls);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) c[q] += (r && cls == q) ? 1 : 0;
+        }
+        int acc = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            nxt[lane * Q + q] = (uint16_t)acc;
+            acc += c[q];
+            lim[lane * Q + q] = (uint16_t)acc;
+            c[q] = acc - c[q];  // running position
+        }
+        for (int t = 0; t < L; ++t) {
+            int cls;
+            if (!real_cls(t, lane, cls)) continue;
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (cls == q) k = c[q]++;
+            order[k * 64 + lane] = (uint16_t)t;
+        }
+    }
+    __syncthreads();
+
+    if (lane < NU) {
+        const int ph = lane / CH, m = lane % CH;
+        int ul[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ul[i] = 32 * (ph >> 1) + 4 * phase_quad(ph & 1, i & 3) + m + CH * (i >> 2);
+        int cnt[Q][Q], rem[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            rem[i] = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                cnt[i][q] = (int)lim[ul[i] * Q + q] - (int)nxt[ul[i] * Q + q];
+                rem[i] += cnt[i][q];
+            }
+        }
+        constexpr int kUnset = -1, kPadPending = 0x200, kPad = 0x100;
+        for (int t = 0; t < L; ++t) {
+            const int rs = L - t;
+            uint32_t used = 0;
+            int pick[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pick[i] = kUnset;
+            // lanes whose entries fill every remaining step, fewest classes first
+            for (int it = 0; it < Q; ++it) {
+                int best = -1, bk = 1 << 30;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    int nz = 0;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) nz += cnt[i][q] > 0 ? 1 : 0;
+                    if (pick[i] == kUnset && rem[i] >= rs && nz < bk) {
+                        bk = nz;
+                        best = i;
+                    }
+                }
+                if (best < 0) break;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (i != best) continue;
+                    int bq = 0, bkey = -1;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int key = cnt[i][q] > 0 ? (((used >> q) & 1u) ? 0 : (1 << 16)) + cnt[i][q] : -1;
+                        if (key > bkey) {
+                            bkey = key;
+                            bq = q;
+                        }
+                    }
+                    pick[i] = bq;
+                    used |= 1u << bq;
+                }
+            }
+            // then lanes with the most entries left, on a free class
+            for (int it = 0; it < Q; ++it) {
+                int best = -1, bk = 0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (pick[i] == kUnset && rem[i] > bk) {
+                        bk = rem[i];
+                        best = i;
+                    }
+                if (best < 0) break;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (i != best) continue;
+                    int bq = -1, bkey = 0;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+                        if (!((used >> q) & 1u) && cnt[i][q] > bkey) {
+                            bkey = cnt[i][q];
+                            bq = q;
+                        }
+                    if (bq >= 0) {
+                        pick[i] = bq;
+                        used |= 1u << bq;
+                    } else {
+                        pick[i] = kPadPending;
+                    }
+                }
+            }
+            // padding on the classes left over
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (pick[i] != kUnset && pick[i] != kPadPending) continue;
+                const uint32_t freeb = ~used & ((1u << Q) - 1u);
+                const int q = freeb ? __builtin_ctz(freeb) : 0;
+                used |= 1u << q;
+                pick[i] = kPad | q;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int l = ul[i];
+                if (pick[i] & kPad) {
+                    src[t * 64 + l] = (uint16_t)(0x8000 | (pick[i] & 0xff));
+                    continue;
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (q != pick[i]) continue;
+                    const int k = nxt[l * Q + q];
+                    nxt[l * Q + q] = (uint16_t)(k + 1);
+                    if (k >= lim[l * Q + q]) atomicOr(err, 8);  // cannot happen: cnt > 0
+                    src[t * 64 + l] = order[min(k, L - 1) * 64 + l];
+                    cnt[i][q] -= 1;
+                    rem[i] -= 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int t = 0; t < L; t += kGroup) {
+        const int64_t g = g0 + t / kGroup;
+        uint32_t e[kGroup];
+        uint16_t sl[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            const int sidx = src[(t + q) * 64 + lane];
+            if (sidx & 0x8000) {
+                e[q] = FMT == XCT_F32 ? 0u : (uint32_t)(sidx & 0xff) << 16;
+                sl[q] = (uint16_t)(sidx & 0xff);
+            } else {
+                e[q] = ent[sidx * 64 + lane];
+                sl[q] = FMT == XCT_F32 ? eslot[sidx * 64 + lane] : 0;
+            }
+        }
+        if constexpr (FMT == XCT_F32) {
+            uint16_t *sp = slot + g * 768 + lane * kGroup;
+            float *vp = val + g * 384 + 128 + lane * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                sp[q] = sl[q];
+                vp[q] = __uint_as_float(e[q]);
+            }
+        } else {
+            uint32_t *pp = packed + (g * kTileSlots + lane) * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) pp[q] = e[q];
+        }
+    }
+    if (lane == 0) atomicAdd(n_done, 1ull);
+}
+
 // ---- host orchestration ---------------------------------------------------
 
 struct DevBuf {
@@ -542,7 +797,7 @@ static void free_op(OpPlan &op) {
 
 template <class Rows>
 static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t n_row_tiles, int64_t n_in_tiles,
-                    int W, int T, int swz, xct_dtype vdt, hipStream_t st) {
+                    int W, int T, int swz, xct_dtype vdt, int row_bytes, int balance, hipStream_t st) {
     op.which = std::is_same<Rows, BackRows>::value ? 1 : 0;
     op.swz = swz;
     op.lanes = rows.lanes;
@@ -659,6 +914,44 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     XCT_HIP_TRY(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
     XCT_HIP_TRY(hipStreamSynchronize(st));
     if (err) return fail(XCT_ERR_INTERNAL, "builder passes disagree on the entry set (code " + std::to_string(err) + ")");
+    op.n_slabs = nlen;
+    op.balanced = 0;
+    // reorder the slabs' steps against LDS bank conflicts (rows of 32 or 64 bytes)
+    const int Q = row_bytes == 64 ? 4 : row_bytes == 32 ? 8 : 0;
+    if (balance && Q && nlen) {
+        int64_t max_len = 0;
+        for (int64_t i = 0; i < nlen; ++i) max_len = std::max<int64_t>(max_len, len[i]);
+        const size_t step = balance_lds_step(vdt), fixed_b = balance_lds_fixed(Q);
+        int64_t cap = ((int64_t)(((size_t)lds_max - fixed_b) / step) / kGroup) * kGroup;
+        cap = std::min<int64_t>(cap, max_len * kGroup);
+        if (cap > 0) {
+            const size_t smem_b = fixed_b + step * (size_t)cap;
+            DevBuf d_done;
+            XCT_HIP_TRY(hipMalloc(&d_done.p, sizeof(unsigned long long)));
+            XCT_HIP_TRY(hipMemsetAsync(d_done.p, 0, sizeof(unsigned long long), st));
+            auto bal = [&](auto kern) -> int {
+                XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)smem_b));
+                hipLaunchKernelGGL(kern, dim3((unsigned)nlen), dim3(64), smem_b, st, op.slab, (int)cap, op.slot,
+                                   op.val, op.packed, (unsigned long long *)d_done.p, (int *)d_err.p);
+                XCT_HIP_TRY(hipGetLastError());
+                return XCT_OK;
+            };
+            if (vdt == XCT_F32)
+                rc = Q == 4 ? bal(k_balance<XCT_F32, 4>) : bal(k_balance<XCT_F32, 8>);
+            else if (vdt == XCT_F16)
+                rc = Q == 4 ? bal(k_balance<XCT_F16, 4>) : bal(k_balance<XCT_F16, 8>);
+            else
+                rc = Q == 4 ? bal(k_balance<XCT_BF16, 4>) : bal(k_balance<XCT_BF16, 8>);
+            if (rc) return rc;
+            unsigned long long done = 0;
+            XCT_HIP_TRY(hipMemcpyAsync(&done, d_done.p, sizeof(done), hipMemcpyDeviceToHost, st));
+            XCT_HIP_TRY(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            XCT_HIP_TRY(hipStreamSynchronize(st));
+            if (err) return fail(XCT_ERR_INTERNAL, "slab reordering lost an entry (code " + std::to_string(err) + ")");
+            op.balanced = (int64_t)done;
+        }
+    }
     const int eb = vdt == XCT_F32 ? 6 : 4;
     op.bytes = op.padded * eb + (int64_t)sizeof(int64_t) * (nlen + 1) + (int64_t)sizeof(int32_t) * op.n_list +
                (int64_t)sizeof(int32_t) * 2 * (nb + 1);
@@ -713,8 +1006,10 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
     if (o.lds_layout < 0 || o.lds_layout > 3) return fail(XCT_ERR_INVALID, "lds_layout must be in [0, 3]");
     if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
-    static const int kLayoutMode[4] = {1, 0, 2, 3};  // option value -> lds_swizzle variant
-    const int swz = lds_swizzle_bits(F * elem_bytes(value_dtype)) | (kLayoutMode[o.lds_layout] << 8);
+    static const int kLayoutMode[4] = {0, 1, 2, 3};  // option value -> lds_swizzle variant
+    if (o.slab_order < 0 || o.slab_order > 1) return fail(XCT_ERR_INVALID, "slab_order must be 0 or 1");
+    const int row_bytes = F * elem_bytes(value_dtype);
+    const int swz = lds_swizzle_bits(row_bytes) | (kLayoutMode[o.lds_layout] << 8);
     const int lanes = o.lane_order;
     auto t0 = std::chrono::steady_clock::now();
     xct_matrix *m = new xct_matrix();
@@ -737,7 +1032,9 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
             order_sweep_proj(m, W, nb, ho);
         DevOrder dord;
         rc = upload_order(ho, m->vol.n_tiles, dord);
-        if (!rc) rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, swz, value_dtype, st);
+        if (!rc)
+            rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, swz, value_dtype, row_bytes,
+                          o.slab_order == 0, st);
     }
     if (!rc) {
         BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW, lanes};
@@ -748,7 +1045,9 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
             order_raster(m->sino, ho);
         DevOrder dord;
         rc = upload_order(ho, m->sino.n_tiles, dord);
-        if (!rc) rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, swz, value_dtype, st);
+        if (!rc)
+            rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, swz, value_dtype, row_bytes,
+                          o.slab_order == 0, st);
     }
     if (rc) {
         std::string msg = g_last_error;
@@ -769,6 +1068,8 @@ static void fill_stats(const OpPlan &op, xct_op_stats &s) {
     s.staged_slots = op.staged_slots;
     s.blocks = op.n_blocks;
     s.tiles_per_stage = op.T;
+    s.slabs = op.n_slabs;
+    s.balanced_slabs = op.balanced;
 }
 
 extern "C" int xct_matrix_info(const xct_matrix *m, xct_matrix_info_t *info) {
@@ -862,8 +1163,8 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
                                 v = m->vdt == XCT_F16 ? half_bits_to_float(bits) : bf16_bits_to_float(bits);
                             }
                             if (v == 0.0f) {
-                                if (m->vdt == XCT_F32 && sidx != 0)
-                                    return fail(XCT_ERR_INTERNAL, "zero-valued entry with a nonzero slot");
+                                // padding points at one of the first 16 rows (its bank class)
+                                if (sidx >= 16) return fail(XCT_ERR_INTERNAL, "padding entry outside rows 0..15");
                                 continue;
                             }
                             if (rt >= op.n_row_tiles)

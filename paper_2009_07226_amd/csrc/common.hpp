@@ -64,18 +64,20 @@ struct OpPlan {
     float *val = nullptr;
     uint32_t *packed = nullptr;
     int64_t nnz = 0, padded = 0, staged_slots = 0, bytes = 0;
+    int64_t n_slabs = 0, balanced = 0;  // (stage, wavefront) slabs; those reordered against bank conflicts
 };
 
-// LDS row placement of the staged input.  A stage holds T*64 rows of
-// F*elem bytes; with L = 2^k rows per 256-byte LDS line the row of slot s is
-// placed at s ^ ((s >> k) & (L-1)) ^ ((s >> 2k) & (L-1)), a permutation within
-// aligned groups of L rows.  Neighbouring rays visit slots that differ in
-// low bits (adjacent columns) or in bits k.. (adjacent rows); the XOR spreads
-// both cases over the banks.  Entries store the placed (physical) slot.  The
-// map XORs the low k bits with a function of higher bits it leaves unchanged,
-// so it is its own inverse.
-// swz packs k (low 8 bits) and a variant (bits 8..15): 0 plain placement,
-// 1 (default) the two-term XOR above, 2 a three-term XOR (bits k.., 2k..,
+// LDS row placement of the staged input (a tuning option).  A stage holds
+// T*64 rows of F*elem bytes; with L = 2^k rows per 256-byte LDS line the
+// XOR variants place the row of slot s at s ^ ((s >> k) & (L-1)) ^
+// ((s >> 2k) & (L-1)) (two-term), a permutation within aligned groups of L
+// rows that spreads neighbouring voxels over the banks.  By default rows are
+// placed plainly (row = slot): the builder's slab schedule already makes the
+// reads of each LDS phase conflict-free.  Entries store the placed
+// (physical) slot.  Each map XORs the low k bits with a function of higher
+// bits it leaves unchanged, so it is its own inverse.
+// swz packs k (low 8 bits) and a variant (bits 8..15): 0 plain placement
+// (default), 1 the two-term XOR above, 2 a three-term XOR (bits k.., 2k..,
 // 3k..), 3 a one-term XOR (bits k.. only).
 __host__ __device__ inline uint32_t lds_swizzle(uint32_t s, int swz) {
     const int k = swz & 0xff, mode = (swz >> 8) & 0xff;

@@ -102,7 +102,8 @@ def test_project_backproject_parity(N, M, C, B):
 @pytest.mark.parametrize("opts", [dict(stage_order=1), dict(tile_waves=4, lds_bytes=32768),
                                   dict(tile_waves=16, xcd_remap=-1), dict(fuse=4), dict(lds_layout=1),
                                   dict(lds_layout=2, lane_order=1), dict(lds_layout=3, tile_waves=16,
-                                                                        lds_bytes=163840)])
+                                                                        lds_bytes=163840),
+                                  dict(slab_order=1), dict(fuse=8), dict(fuse=8, lds_layout=1)])
 def test_plan_options_keep_parity(opts):
     N, M, C, B = 64, 90, 64, 5
     A = gpu_matrix(N, M, C, **opts)
@@ -112,6 +113,18 @@ def test_plan_options_keep_parity(opts):
     assert rel_err(y.numpy(), oracle.project(Ao, x.double().numpy().reshape(B, -1))).max() <= 1e-5
     xb = xct.backproject(A, y.cuda()).cpu()
     assert rel_err(xb.numpy(), oracle.backproject(ATo, y.double().numpy())).max() <= 1e-5
+
+
+@pytest.mark.parametrize("dt,kw,expect", [("f32", {}, True), ("f16", {}, True), ("bf16", {}, True),
+                                           ("f32", dict(fuse=8), True), ("f32", dict(slab_order=1), False),
+                                           ("f32", dict(fuse=4), False), ("f16", dict(fuse=8), False)])
+def test_slab_scheduling_applied(dt, kw, expect):
+    # rows of 32 or 64 bytes get the bank-conflict schedule, every slab of it
+    A = gpu_matrix(128, 180, 128, dt, **kw)
+    for op in ("A", "AT"):
+        st = A.info()[op]
+        assert st["slabs"] > 0
+        assert st["balanced_slabs"] == (st["slabs"] if expect else 0), st
 
 
 def test_output_shape_and_zero_input():
