@@ -429,19 +429,16 @@ inline size_t balance_lds_step(xct_dtype vdt) { return (size_t)kTileSlots * (vdt
 inline size_t balance_lds_fixed(int Q) { return (size_t)2 * kTileSlots * Q * sizeof(uint16_t); }
 
 template <int FMT, int Q>
-__global__ void __launch_bounds__(64) k_balance(const int64_t *slab, int L_cap, uint16_t *slot, float *val,
-                                                uint32_t *packed, unsigned long long *n_done, int *err) {
+__global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32_t *ids, int L_cap, uint16_t *slot,
+                                                float *val, uint32_t *packed, unsigned long long *n_done, int *err) {
     constexpr int CH = 16 / Q;  // chunks per staged row
     constexpr int NU = 64 / Q;  // units per wavefront
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x;
-    const int64_t g0 = slab[blockIdx.x];
-    const int L = (int)(slab[blockIdx.x + 1] - g0) * kGroup;
-    if (L > L_cap) return;  // whole workgroup; left in tracing order
-    if (L == 0) {
-        if (lane == 0) atomicAdd(n_done, 1ull);
-        return;
-    }
+    const int64_t sid = ids[blockIdx.x];
+    const int64_t g0 = slab[sid];
+    const int L = (int)(slab[sid + 1] - g0) * kGroup;
+    if (L == 0 || L > L_cap) return;  // whole workgroup (the host sorts slabs by length)
     char *p = smem;
     uint32_t *ent = (uint32_t *)p;  // F32: length bits; 16-bit: packed entry
     p += sizeof(uint32_t) * (size_t)L * 64;
@@ -517,13 +514,16 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, int L_cap, 
         int ul[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) ul[i] = 32 * (ph >> 1) + 4 * phase_quad(ph & 1, i & 3) + m + CH * (i >> 2);
-        int cnt[Q][Q], rem[Q];
+        // per lane and class: entries left (cnt) and the end of the class in
+        // order[] (end); the next entry of the class is order[end - cnt]
+        int cnt[Q][Q], end[Q][Q], rem[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             rem[i] = 0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                cnt[i][q] = (int)lim[ul[i] * Q + q] - (int)nxt[ul[i] * Q + q];
+                end[i][q] = lim[ul[i] * Q + q];
+                cnt[i][q] = end[i][q] - (int)nxt[ul[i] * Q + q];
                 rem[i] += cnt[i][q];
             }
         }
@@ -611,10 +611,9 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, int L_cap, 
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     if (q != pick[i]) continue;
-                    const int k = nxt[l * Q + q];
-                    nxt[l * Q + q] = (uint16_t)(k + 1);
-                    if (k >= lim[l * Q + q]) atomicOr(err, 8);  // cannot happen: cnt > 0
-                    src[t * 64 + l] = order[min(k, L - 1) * 64 + l];
+                    const int k = end[i][q] - cnt[i][q];
+                    if (cnt[i][q] <= 0) atomicOr(err, 8);  // cannot happen: a class is picked with entries left
+                    src[t * 64 + l] = order[min(max(k, 0), L - 1) * 64 + l];
                     cnt[i][q] -= 1;
                     rem[i] -= 1;
                 }
@@ -919,21 +918,42 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     // reorder the slabs' steps against LDS bank conflicts (rows of 32 or 64 bytes)
     const int Q = row_bytes == 64 ? 4 : row_bytes == 32 ? 8 : 0;
     if (balance && Q && nlen) {
-        int64_t max_len = 0;
-        for (int64_t i = 0; i < nlen; ++i) max_len = std::max<int64_t>(max_len, len[i]);
         const size_t step = balance_lds_step(vdt), fixed_b = balance_lds_fixed(Q);
-        int64_t cap = ((int64_t)(((size_t)lds_max - fixed_b) / step) / kGroup) * kGroup;
-        cap = std::min<int64_t>(cap, max_len * kGroup);
-        if (cap > 0) {
-            const size_t smem_b = fixed_b + step * (size_t)cap;
-            DevBuf d_done;
-            XCT_HIP_TRY(hipMalloc(&d_done.p, sizeof(unsigned long long)));
-            XCT_HIP_TRY(hipMemsetAsync(d_done.p, 0, sizeof(unsigned long long), st));
+        const int64_t cap = ((int64_t)(((size_t)lds_max - fixed_b) / step) / kGroup) * kGroup;
+        // slabs by length: each launch sizes its LDS for its longest slab, so
+        // the many short slabs run many workgroups per CU
+        const int64_t bucket_cap[4] = {32, 64, 128, cap};
+        std::vector<int32_t> ids[4];
+        int64_t empty = 0;
+        for (int64_t i = 0; i < nlen; ++i) {
+            const int64_t L = (slab[i + 1] - slab[i]) * kGroup;  // slab i in slab (wave-major) order
+            if (L == 0) {
+                ++empty;
+                continue;
+            }
+            for (int k = 0; k < 4; ++k)
+                if (L <= bucket_cap[k] && L <= cap) {
+                    ids[k].push_back((int32_t)i);
+                    break;
+                }
+        }
+        DevBuf d_done;
+        XCT_HIP_TRY(hipMalloc(&d_done.p, sizeof(unsigned long long)));
+        XCT_HIP_TRY(hipMemsetAsync(d_done.p, 0, sizeof(unsigned long long), st));
+        std::vector<DevBuf> d_ids(4);
+        for (int k = 0; k < 4; ++k) {
+            if (ids[k].empty()) continue;
+            const int64_t bc = std::min(bucket_cap[k], cap);
+            const size_t smem_b = fixed_b + step * (size_t)bc;
+            XCT_HIP_TRY(hipMalloc(&d_ids[k].p, sizeof(int32_t) * ids[k].size()));
+            XCT_HIP_TRY(hipMemcpyAsync(d_ids[k].p, ids[k].data(), sizeof(int32_t) * ids[k].size(),
+                                       hipMemcpyHostToDevice, st));
             auto bal = [&](auto kern) -> int {
                 XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                 (int)smem_b));
-                hipLaunchKernelGGL(kern, dim3((unsigned)nlen), dim3(64), smem_b, st, op.slab, (int)cap, op.slot,
-                                   op.val, op.packed, (unsigned long long *)d_done.p, (int *)d_err.p);
+                hipLaunchKernelGGL(kern, dim3((unsigned)ids[k].size()), dim3(64), smem_b, st, op.slab,
+                                   (const int32_t *)d_ids[k].p, (int)bc, op.slot, op.val, op.packed,
+                                   (unsigned long long *)d_done.p, (int *)d_err.p);
                 XCT_HIP_TRY(hipGetLastError());
                 return XCT_OK;
             };
@@ -944,13 +964,13 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
             else
                 rc = Q == 4 ? bal(k_balance<XCT_BF16, 4>) : bal(k_balance<XCT_BF16, 8>);
             if (rc) return rc;
-            unsigned long long done = 0;
-            XCT_HIP_TRY(hipMemcpyAsync(&done, d_done.p, sizeof(done), hipMemcpyDeviceToHost, st));
-            XCT_HIP_TRY(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
-            XCT_HIP_TRY(hipStreamSynchronize(st));
-            if (err) return fail(XCT_ERR_INTERNAL, "slab reordering lost an entry (code " + std::to_string(err) + ")");
-            op.balanced = (int64_t)done;
         }
+        unsigned long long done = 0;
+        XCT_HIP_TRY(hipMemcpyAsync(&done, d_done.p, sizeof(done), hipMemcpyDeviceToHost, st));
+        XCT_HIP_TRY(hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        XCT_HIP_TRY(hipStreamSynchronize(st));
+        if (err) return fail(XCT_ERR_INTERNAL, "slab reordering lost an entry (code " + std::to_string(err) + ")");
+        op.balanced = (int64_t)done + empty;  // empty slabs are trivially conflict-free
     }
     const int eb = vdt == XCT_F32 ? 6 : 4;
     op.bytes = op.padded * eb + (int64_t)sizeof(int64_t) * (nlen + 1) + (int64_t)sizeof(int32_t) * op.n_list +

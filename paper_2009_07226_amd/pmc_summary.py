@@ -1,10 +1,16 @@
-"""Summarise rocprofv3 counter runs of the SpMM kernel into HBM traffic per launch.
+"""Summarise rocprofv3 runs of the SpMM kernel: HBM traffic per launch from
+counter runs, and kernel-time tables from kernel-trace runs.
 
-Usage (after two rocprofv3 --pmc runs of bench.py with --copy-calibration-mib,
+Traffic (after two rocprofv3 --pmc runs of bench.py with --copy-calibration-mib,
 one collecting FETCH_SIZE and one WRITE_SIZE, each with -f csv):
 
     python -m paper_2009_07226_amd.pmc_summary FETCH.csv WRITE.csv OUT_PREFIX \
         --copy-mib 1024 --command "<the rocprofv3 commands>"
+
+Kernel times (after rocprofv3 --kernel-trace --stats -f csv):
+
+    python -m paper_2009_07226_amd.pmc_summary --trace KERNEL_STATS.csv OUT.md \
+        --command "<the rocprofv3 command>" --workload "<workload>"
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Their scale on a
 given device is calibrated with the plain device copy of known size that
@@ -65,15 +71,36 @@ def summarise(fetch_csv, write_csv, copy_mib):
     return out
 
 
+def trace_table(stats_csv, out_md, command, workload, note=""):
+    """Markdown table of a rocprofv3 kernel_stats.csv (durations in ns)."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# Kernel times: {workload}", "", "Command:", "", "```", command, "```", "",
+             "| Kernel | Calls | Total ns | Average ns | % | Min ns | Max ns |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].replace("void ", "").split("(")[0]
+        lines.append(f"| {name} | {r['Calls']} | {int(float(r['TotalDurationNs']))} | {float(r['AverageNs']):.0f} | "
+                     f"{float(r['Percentage']):.2f} | {int(float(r['MinNs']))} | {int(float(r['MaxNs']))} |")
+    if note:
+        lines += ["", note]
+    lines += ["", f"Kernel sources SHA-256: `{kernel_sources_sha()}`"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_csv")
-    ap.add_argument("write_csv")
-    ap.add_argument("out_prefix")
+    ap.add_argument("write_csv", nargs="?")
+    ap.add_argument("out_prefix", nargs="?")
+    ap.add_argument("--trace", action="store_true", help="fetch_csv is a kernel_stats.csv, write_csv the output .md")
+    ap.add_argument("--note", default="")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
     a = ap.parse_args()
+    if a.trace:
+        trace_table(a.fetch_csv, a.write_csv, a.command, a.workload, a.note)
+        return
     s = summarise(a.fetch_csv, a.write_csv, a.copy_mib)
     s["kernel_sources_sha256"] = kernel_sources_sha()
     s["command"] = a.command
