@@ -200,18 +200,10 @@ def main():
     log(f"step {ms_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {value:.1f} GB/s; "
         f"SpMM A {msA / max(nA, 1):.3f} ms, A^T {msT / max(nT, 1):.3f} ms per launch")
 
-    # context: what a plain streaming read reaches on this device (torch
-    # reduction over 4 GiB, inputs resident)
+    # context: what a plain streaming read (16-byte non-temporal loads) reaches
+    # on this device over 4 GiB resident in HBM
     big = torch.ones(1 << 30, dtype=torch.float32, device=dev)
-    big.sum()
-    torch.cuda.synchronize()
-    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    r0.record()
-    for _ in range(5):
-        big.sum()
-    r1.record()
-    torch.cuda.synchronize()
-    read_ceiling = 5 * big.numel() * 4 / (r0.elapsed_time(r1) * 1e-3) / 1e9
+    read_ceiling = xct.read_bandwidth(big, reps=5)
     del big
     torch.cuda.empty_cache()
 

@@ -213,6 +213,12 @@ int xct_matrix_to_coo(const xct_matrix *A, int which, int32_t *rows, int32_t *co
 int xct_profile_enable(int on);
 int xct_profile_read(int64_t *launches, double *ms);
 
+/* Measurement utility: streaming-read bandwidth of the device (GB/s, 1e9 B/s)
+ * over the caller's device buffer of `bytes` bytes (>= 16; read only),
+ * `reps` timed passes after one untimed pass, on `stream`; blocks until done.
+ * The reference ceiling for the SpMM's matrix stream; not part of the method. */
+int xct_read_bandwidth(const void *buf, int64_t bytes, int reps, double *gbps, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *xct_last_error(void);
 

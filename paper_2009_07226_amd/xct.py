@@ -91,6 +91,8 @@ def lib():
     L.xct_profile_enable.restype = i
     L.xct_profile_read.argtypes = [vp, vp]
     L.xct_profile_read.restype = i
+    L.xct_read_bandwidth.argtypes = [vp, i64, i, ctypes.POINTER(ctypes.c_double), vp]
+    L.xct_read_bandwidth.restype = i
     L.xct_last_error.argtypes = []
     L.xct_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -263,6 +265,16 @@ def profile_read() -> dict:
     ms = np.zeros(2, np.float64)
     _check(lib().xct_profile_read(n.ctypes.data, ms.ctypes.data))
     return {"A": (int(n[0]), float(ms[0])), "AT": (int(n[1]), float(ms[1]))}
+
+
+def read_bandwidth(buf: torch.Tensor, reps: int = 5, stream=None) -> float:
+    """Streaming-read GB/s of the device over a resident tensor (measurement utility)."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous CUDA tensor")
+    g = ctypes.c_double()
+    _check(lib().xct_read_bandwidth(buf.data_ptr(), buf.numel() * buf.element_size(), int(reps), ctypes.byref(g),
+                                    _stream(stream)))
+    return g.value
 
 
 class XctProject(torch.autograd.Function):

@@ -43,3 +43,6 @@ def test_argument_errors_without_device():
     assert L.xct_cgls(None, None, 0, None, 1, 1, None, None, None, None) == -1
     assert L.xct_spmm_workspace_bytes(None, 4) == 0
     assert L.xct_cgls_workspace_bytes(None, 4, 3) == 0
+    g = ctypes.c_double()
+    assert L.xct_read_bandwidth(None, 1 << 20, 1, ctypes.byref(g), None) == -1
+    assert L.xct_profile_read(None, None) == -1
