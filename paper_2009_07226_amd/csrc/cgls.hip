@@ -164,15 +164,25 @@ __global__ void k_cast16(const float *v, int64_t n, int F, const float *inv, uin
 
 // ---- per-slice scalar updates --------------------------------------------------
 
-// sum[b] = sum over blocks of part[m][blk][f], b = m*F + f, fixed order.
-__global__ void k_reduce(const double *part, int64_t stride, int nblk, int F, int Bp, double *sum) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= Bp) return;
+// sum[b] = sum over blocks of part[m][blk][f], b = m*F + f: one workgroup per
+// slice, thread t adding blocks t, t + 256, ... in order, then a fixed
+// pairwise tree in LDS, so the result is the same on every run.
+constexpr int kReduceThreads = 256;
+__global__ void __launch_bounds__(kReduceThreads) k_reduce(const double *part, int64_t stride, int nblk, int F,
+                                                           double *sum) {
+    __shared__ double red[kReduceThreads];
+    const int b = blockIdx.x, t = threadIdx.x;
     const int m = b / F, f = b % F;
     const double *p = part + (int64_t)m * stride * F;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += p[(int64_t)k * F + f];
-    sum[b] = s;
+    for (int k = t; k < nblk; k += kReduceThreads) s += p[(int64_t)k * F + f];
+    red[t] = s;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) sum[b] = red[0];
 }
 
 enum { kSetGamma = 0, kSetAlpha = 1, kSetBeta = 2, kSetYY = 3, kSetResid = 4 };
@@ -236,7 +246,7 @@ struct Cgls {
     }
 
     int reduce(const double *part, int64_t stride, int nblk) {
-        hipLaunchKernelGGL(k_reduce, dim3((w.Bp + 255) / 256), dim3(256), 0, st, part, stride, nblk, w.F, w.Bp, w.sum);
+        hipLaunchKernelGGL(k_reduce, dim3(w.Bp), dim3(kReduceThreads), 0, st, part, stride, nblk, w.F, w.sum);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
     }

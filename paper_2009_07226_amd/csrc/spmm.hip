@@ -536,6 +536,11 @@ struct ConvArgs {
     int io, storage;
 };
 
+// Natural [B][H][Wd] <-> internal [tile][64][F].  One thread per slot: the F
+// loads (or stores) of the natural side are issued together (coalesced over
+// the 8 x 8 tile of a wavefront), the internal side is one contiguous row
+// written (or read) with 16-byte accesses.
+template <int F>
 __global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const float *inv) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= c.n_tiles * kTileSlots) return;
@@ -545,17 +550,49 @@ __global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const
     const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
     const bool in = row < c.H && col < c.Wd;
     const int64_t plane = (int64_t)c.H * c.Wd;
-    for (int f = 0; f < c.F; ++f) {
+    const int64_t pix = (int64_t)row * c.Wd + col;
+    float v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
         const int s = c.s0 + f;
-        float v = 0.f;
-        if (in && s < c.batch) {
-            v = load_io(nat, (int64_t)s * plane + (int64_t)row * c.Wd + col, c.io);
-            if (inv) v *= inv[f];
+        v[f] = (in && s < c.batch) ? load_io(nat, (int64_t)s * plane + pix, c.io) : 0.f;
+    }
+    if (inv) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] *= inv[f];
+    }
+    if (c.storage == XCT_F32) {
+        float *dst = (float *)internal + t * F;
+        if constexpr (F >= 4) {
+#pragma unroll
+            for (int q = 0; q < F / 4; ++q) ((f32x4 *)dst)[q] = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) dst[f] = v[f];
         }
-        store_io(internal, t * c.F + f, v, c.storage);
+    } else {
+        uint16_t h[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) h[f] = (uint16_t)(c.storage == XCT_F16 ? f32_to_h16(v[f]) : f32_to_bf16(v[f]));
+        uint16_t *dst = (uint16_t *)internal + t * F;
+        if constexpr (F >= 8) {
+#pragma unroll
+            for (int q = 0; q < F / 8; ++q) {
+                u32x4 w;
+                w.x = h[8 * q] | ((uint32_t)h[8 * q + 1] << 16);
+                w.y = h[8 * q + 2] | ((uint32_t)h[8 * q + 3] << 16);
+                w.z = h[8 * q + 4] | ((uint32_t)h[8 * q + 5] << 16);
+                w.w = h[8 * q + 6] | ((uint32_t)h[8 * q + 7] << 16);
+                ((u32x4 *)dst)[q] = w;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f) dst[f] = h[f];
+        }
     }
 }
 
+template <int F>
 __global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= c.n_tiles * kTileSlots) return;
@@ -565,10 +602,26 @@ __global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
     const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
     if (row >= c.H || col >= c.Wd) return;
     const int64_t plane = (int64_t)c.H * c.Wd;
-    for (int f = 0; f < c.F; ++f) {
+    const int64_t pix = (int64_t)row * c.Wd + col;
+    float v[F];
+    const float *src = internal + t * F;
+    if constexpr (F >= 4) {
+#pragma unroll
+        for (int q = 0; q < F / 4; ++q) {
+            const f32x4 w = ((const f32x4 *)src)[q];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = src[f];
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
         const int s = c.s0 + f;
-        if (s >= c.batch) break;
-        store_io(nat, (int64_t)s * plane + (int64_t)row * c.Wd + col, internal[t * c.F + f], c.io);
+        if (s < c.batch) store_io(nat, (int64_t)s * plane + pix, v[f], c.io);
     }
 }
 
@@ -626,7 +679,15 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
                        xct_dtype storage, const float *inv_scale, hipStream_t st) {
     const ConvArgs c = conv_args(g, batch, s0, F, io, storage);
     const int64_t n = g.n_tiles * kTileSlots;
-    hipLaunchKernelGGL(k_to_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, nat, internal, inv_scale);
+    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    switch (F) {
+        case 1: hipLaunchKernelGGL(k_to_internal<1>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 2: hipLaunchKernelGGL(k_to_internal<2>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 4: hipLaunchKernelGGL(k_to_internal<4>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 8: hipLaunchKernelGGL(k_to_internal<8>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 16: hipLaunchKernelGGL(k_to_internal<16>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    }
     XCT_HIP_TRY(hipGetLastError());
     return XCT_OK;
 }
@@ -635,7 +696,15 @@ int launch_from_internal(const Grid &g, const float *internal, int batch, int s0
                          hipStream_t st) {
     const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F32);
     const int64_t n = g.n_tiles * kTileSlots;
-    hipLaunchKernelGGL(k_from_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, internal, nat);
+    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    switch (F) {
+        case 1: hipLaunchKernelGGL(k_from_internal<1>, grid, blk, 0, st, c, internal, nat); break;
+        case 2: hipLaunchKernelGGL(k_from_internal<2>, grid, blk, 0, st, c, internal, nat); break;
+        case 4: hipLaunchKernelGGL(k_from_internal<4>, grid, blk, 0, st, c, internal, nat); break;
+        case 8: hipLaunchKernelGGL(k_from_internal<8>, grid, blk, 0, st, c, internal, nat); break;
+        case 16: hipLaunchKernelGGL(k_from_internal<16>, grid, blk, 0, st, c, internal, nat); break;
+        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    }
     XCT_HIP_TRY(hipGetLastError());
     return XCT_OK;
 }
