@@ -123,7 +123,7 @@ __device__ __forceinline__ Group<FMT> load_group(const SpmmArgs &a, int64_t gi, 
 }
 
 template <int FMT, int F>
-__device__ __forceinline__ void use_group(const Group<FMT> &g, const char *lds, const int (&coff)[RowShape<FMT, F>::CH],
+__device__ __forceinline__ void use_group(const Group<FMT> &g, const char *const (&cbase)[RowShape<FMT, F>::CH],
                                           float (&acc)[F]) {
     typedef RowShape<FMT, F> R;
     uint32_t sl[kGroup];
@@ -147,14 +147,14 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const char *lds, 
     }
 #pragma unroll
     for (int q = 0; q < kGroup; ++q) {
-        const char *row = lds + sl[q] * R::RB;
+        const uint32_t roff = sl[q] * R::RB;
 #pragma unroll
         for (int j = 0; j < R::CH; ++j) {
             u32x4 w;
             if constexpr (R::RB >= 16)
-                w = *(const u32x4 *)(row + coff[j]);
+                w = *(const u32x4 *)(cbase[j] + roff);
             else
-                w = load_small<R::RB>(row);
+                w = load_small<R::RB>(cbase[0] + roff);
             float x[R::SPC];
             expand<FMT, R::SPC>(w, x);
 #pragma unroll
@@ -205,8 +205,12 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     // of one LDS cycle spread over the chunks; accumulator block j holds the
     // slices of that rotated chunk.
     int coff[R::CH];
+    const char *cbase[R::CH];  // LDS address of this lane's chunk j of row 0
 #pragma unroll
-    for (int j = 0; j < R::CH; ++j) coff[j] = ((j + lane) & (R::CH - 1)) * 16;
+    for (int j = 0; j < R::CH; ++j) {
+        coff[j] = ((j + lane) & (R::CH - 1)) * 16;
+        cbase[j] = smem + coff[j];
+    }
     float acc[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) acc[f] = 0.f;
@@ -317,7 +321,7 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
             for (int d = 0; d < D; ++d) {
                 const int k = i + d;
                 if (k >= 0 && k < n) {
-                    use_group<FMT, F>(e[d], smem, coff, acc);
+                    use_group<FMT, F>(e[d], cbase, acc);
                     sg[d] = take();
                 }
                 e[d] = load_group<FMT>(a, sg[d], lane);
