@@ -850,7 +850,9 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     int rc = upload(&op.blk_tile, blk_tile);
     if (!rc) rc = upload(&op.blk_stage, blk_stage);
     if (rc) return rc;
-    XCT_HIP_TRY(hipMalloc((void **)&op.tile_list, sizeof(int32_t) * std::max<int64_t>(1, op.n_list)));
+    // 4 entries of padding: the SpMM reads the list four entries at a time
+    XCT_HIP_TRY(hipMalloc((void **)&op.tile_list, sizeof(int32_t) * (op.n_list + 4)));
+    XCT_HIP_TRY(hipMemsetAsync(op.tile_list, 0, sizeof(int32_t) * (op.n_list + 4), st));
     const int64_t nlen = op.n_stages * W;
     XCT_HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * std::max<int64_t>(1, nlen)));
     XCT_HIP_TRY(hipMalloc(&d_err.p, sizeof(int)));
@@ -1029,7 +1031,8 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     static const int kLayoutMode[4] = {0, 1, 2, 3};  // option value -> lds_swizzle variant
     if (o.slab_order < 0 || o.slab_order > 1) return fail(XCT_ERR_INVALID, "slab_order must be 0 or 1");
     const int row_bytes = F * elem_bytes(value_dtype);
-    const int swz = lds_swizzle_bits(row_bytes) | (kLayoutMode[o.lds_layout] << 8);
+    // FP32 stages are copied straight into LDS, which needs plain rows
+    const int swz = value_dtype == XCT_F32 ? 0 : lds_swizzle_bits(row_bytes) | (kLayoutMode[o.lds_layout] << 8);
     const int lanes = o.lane_order;
     auto t0 = std::chrono::steady_clock::now();
     xct_matrix *m = new xct_matrix();

@@ -163,6 +163,42 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const char *const
     }
 }
 
+// One 16-byte-per-lane copy from global memory straight into LDS: lane l's
+// 16 bytes at g land at LDS byte lds_addr + 16 l (lds_addr wave-uniform).
+// Written as inline asm: the compiler does not count it in its vmcnt waits
+// (waits it derives are then only ever stricter), and the copy loop waits
+// for it explicitly.  M0 carries the LDS address and is restored.  No memory
+// clobber (which would turn the read-only metadata loads into vector loads
+// with full waits): the asm is volatile and sits between the stage barriers,
+// which order every LDS access around it.
+__device__ __forceinline__ void copy_to_lds16(const void *g, uint32_t lds_addr) {
+    uint32_t saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %2, off\n\t"
+        "s_nop 0\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "s"(lds_addr), "v"(g));
+}
+
+// Wait until no vector-memory operation of this wavefront is outstanding
+// (asm without a memory clobber, for the same reason as above).
+__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)"); }
+
+// Scalar loads of wave-uniform metadata (p wave-uniform).  Once a loop holds
+// inline asm, the compiler no longer proves these read-only arrays unwritten
+// and turns plain loads of them into vector loads followed by full vmcnt
+// waits; these stay on the scalar unit.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ i32x4 sload_x4(const void *p) {
+    i32x4 v;
+    asm volatile("s_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p));
+    return v;
+}
+
 // Issue priority of a wavefront from the groups it has left in the stage.
 // The SIMD arbiter otherwise favours the oldest wavefronts of the workgroup,
 // so the youngest ones finish each stage last and the stage barrier waits
@@ -216,6 +252,8 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     for (int f = 0; f < F; ++f) acc[f] = 0.f;
 
     constexpr int kVecPerTile = kTileSlots * R::RB / 16;  // 16-byte vectors per staged tile
+    // FP32 stages are copied with LDS DMA (16-bit ones by claimed chunks)
+    constexpr bool kDma = FMT == XCT_F32 && R::RB >= 16;
     const int s0 = a.blk_stage[b], s1 = a.blk_stage[b + 1];
     const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
     const u32x4 *xin = (const u32x4 *)a.xin;
@@ -250,7 +288,35 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     // at tile-list position q0 comes from tile tile_list[q0 + c / kVecPerTile]
     // and goes to the placed row of its slot.
     auto copy_static = [&](int q0, int nt) {
-        if constexpr (R::RB >= 16) {
+        if constexpr (kDma) {
+            // Rows placed plainly: a tile's rows are contiguous in LDS, so each
+            // 1 KB piece (64 vectors) is copied straight into LDS with no
+            // registers, the whole stage in flight at once.  Wave w copies
+            // the consecutive pieces [c0, c1); their tiles' indices come four
+            // at a time (the tile list is padded by 4 entries).
+            constexpr int kPiece = kVecPerTile >= 64 ? kVecPerTile / 64 : 1;
+            const int pieces = nt * kPiece, per = (pieces + W - 1) / W;
+            const int c0 = min(pieces, wave * per), c1 = min(pieces, c0 + per);
+            const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)smem;
+            if (c0 < c1) {
+                int base = c0 / kPiece;
+                i32x4 tl = sload_x4(a.tile_list + q0 + base);
+                for (int c = c0; c < c1; ++c) {
+                    const int q = c / kPiece, part = c - q * kPiece;
+                    if (q - base >= 4) {
+                        base = q;
+                        tl = sload_x4(a.tile_list + q0 + base);
+                    }
+                    const int j = q - base;
+                    const int tile = j == 0 ? tl.x : j == 1 ? tl.y : j == 2 ? tl.z : tl.w;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(xin + (int64_t)tile * kVecPerTile + part * 64 + lane),
+                        (__attribute__((address_space(3))) void *)(smem + (size_t)(q * kVecPerTile + part * 64) * 16),
+                        16, 0, 0);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's pieces are in LDS
+        } else if constexpr (R::RB >= 16) {
             // A tile is a multiple of 64 vectors, so the tile of each copied
             // vector is wave-uniform (a scalar load); all loads of a batch are
             // issued before their stores.
@@ -311,7 +377,13 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     __syncthreads();
 
     for (int s = s0; s < s1; ++s) {
-        const int n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
+        int n;
+        if constexpr (kDma) {
+            const i32x4 sb = sload_x4(a.slab + p0 + (s - s0));  // two int64 bounds
+            n = sb.z - sb.x;  // a slab holds far fewer than 2^31 groups
+        } else {
+            n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
+        }
         // consume this stage's n groups, the first one in slot ph; every
         // consumed slot is refilled from the cursor, possibly with a later
         // stage's group
