@@ -110,7 +110,6 @@ def main():
     ap.add_argument("--stage-order", type=int, default=0, help="0 sweep (default), 1 Hilbert")
     ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--tile-waves", type=int, default=0)
-    ap.add_argument("--lds-layout", type=int, default=0)
     ap.add_argument("--lane-order", type=int, default=0)
     ap.add_argument("--slab-order", type=int, default=0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -140,7 +139,7 @@ def main():
 
     log(f"building {args.dtype} matrix N={N} M={M} C={C}")
     opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves,
-                lds_layout=args.lds_layout, lane_order=args.lane_order, slab_order=args.slab_order)
+                lane_order=args.lane_order, slab_order=args.slab_order)
     A = xct.Matrix(N, M, C, args.dtype, **opts)
     b_a = 6 if args.dtype == "f32" else 4
     b_x = 4 if args.dtype == "f32" else 2
@@ -247,7 +246,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.dtype, N, M, B,
                                         not (args.stage_order or args.lds_bytes or args.tile_waves or
-                                             args.lds_layout or args.lane_order or args.slab_order)),
+                                             args.lane_order or args.slab_order)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": {"A": kern_bytes_A, "AT": kern_bytes_AT},

@@ -71,18 +71,15 @@ enum {
 typedef struct {
     int tile_waves; /* row tiles (64 rows each, one wavefront) per workgroup; default 16, max 16 */
     int fuse;       /* largest number of slices fused per matrix pass (F); 1,2,4,8 or 16; default 16 */
-    int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input (plus
-                       256 bytes of counters for FP16/BF16 matrices); default: all of the
-                       device's LDS per workgroup (160 KiB on gfx950) */
+    int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input
+                       (T = lds_bytes / (64 * F * element size) input tiles, at most 1024);
+                       default: all of the device's LDS per workgroup (160 KiB on gfx950) */
     int xcd_remap;  /* 1 (default): consecutive workgroups of the Hilbert order run on the
                        same XCD; -1: plain order */
     int stage_order; /* order in which a workgroup stages its input tiles:
                         0 (default) sweep: for A, by distance along the workgroup's mean ray
                           direction; for A^T, angle-major;
                         1 Hilbert: along the pseudo-Hilbert curve of the input tiles */
-    int lds_layout;  /* tuning: placement of staged rows in LDS; 0 default (plain: row = slot;
-                        bank conflicts are handled by the slab schedule), 1 two-term XOR,
-                        2 three-term XOR, 3 one-term XOR of the slot's bit fields */
     int lane_order;  /* tuning: assignment of a tile's 64 rows to the lanes of a wavefront;
                         0 default (row-major), 1 transposed */
     int slab_order;  /* order of a lane's entries within a (stage, wavefront) slab:

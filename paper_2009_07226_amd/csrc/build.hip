@@ -351,7 +351,7 @@ __global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
 }
 
 template <class Rows, int FMT>
-__global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW, int swz,
+__global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW,
                        const int32_t *blk_stage, const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed,
                        int *err) {
     extern __shared__ __align__(16) char smem[];
@@ -384,7 +384,7 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
                     return;
                 }
                 const int64_t idx = (g * kTileSlots + lane) * kGroup + (n % kGroup);
-                const uint32_t s = lds_swizzle((uint32_t)((pos % T) * kTileSlots + off), swz);
+                const uint32_t s = (uint32_t)((pos % T) * kTileSlots + off);
                 if (FMT == XCT_F32) {
                     const int64_t li = (int64_t)lane * kGroup + (n % kGroup);
                     slot[g * 768 + li] = (uint16_t)s;
@@ -796,9 +796,8 @@ static void free_op(OpPlan &op) {
 
 template <class Rows>
 static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t n_row_tiles, int64_t n_in_tiles,
-                    int W, int T, int swz, xct_dtype vdt, int row_bytes, int balance, hipStream_t st) {
+                    int W, int T, xct_dtype vdt, int row_bytes, int balance, hipStream_t st) {
     op.which = std::is_same<Rows, BackRows>::value ? 1 : 0;
-    op.swz = swz;
     op.lanes = rows.lanes;
     op.n_row_tiles = n_row_tiles;
     op.n_in_tiles = n_in_tiles;
@@ -899,7 +898,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     auto fill = [&](auto kern) -> int {
         XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem_win));
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW, op.swz,
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW,
                            op.blk_stage, op.slab, op.slot, op.val, op.packed, (int *)d_err.p);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
@@ -1021,18 +1020,13 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     he = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (he != hipSuccess) return fail(XCT_ERR_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
     if (!lds) lds = lds_max;  // one workgroup of 16 waves per CU with the whole LDS
-    const int reserve = lds_reserve(value_dtype);
-    if (lds < per_tile + reserve || lds > lds_max)
+    if (lds < per_tile || lds > lds_max)
         return fail(XCT_ERR_INVALID, "lds_bytes must hold one tile and fit the device LDS");
-    int T = (lds - reserve) / per_tile;
+    int T = lds / per_tile;
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
-    if (o.lds_layout < 0 || o.lds_layout > 3) return fail(XCT_ERR_INVALID, "lds_layout must be in [0, 3]");
     if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
-    static const int kLayoutMode[4] = {0, 1, 2, 3};  // option value -> lds_swizzle variant
     if (o.slab_order < 0 || o.slab_order > 1) return fail(XCT_ERR_INVALID, "slab_order must be 0 or 1");
     const int row_bytes = F * elem_bytes(value_dtype);
-    // FP32 stages are copied straight into LDS, which needs plain rows
-    const int swz = value_dtype == XCT_F32 ? 0 : lds_swizzle_bits(row_bytes) | (kLayoutMode[o.lds_layout] << 8);
     const int lanes = o.lane_order;
     auto t0 = std::chrono::steady_clock::now();
     xct_matrix *m = new xct_matrix();
@@ -1056,7 +1050,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         DevOrder dord;
         rc = upload_order(ho, m->vol.n_tiles, dord);
         if (!rc)
-            rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, swz, value_dtype, row_bytes,
+            rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, value_dtype, row_bytes,
                           o.slab_order == 0, st);
     }
     if (!rc) {
@@ -1069,7 +1063,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         DevOrder dord;
         rc = upload_order(ho, m->sino.n_tiles, dord);
         if (!rc)
-            rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, swz, value_dtype, row_bytes,
+            rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, row_bytes,
                           o.slab_order == 0, st);
     }
     if (rc) {
@@ -1192,9 +1186,7 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
                             }
                             if (rt >= op.n_row_tiles)
                                 return fail(XCT_ERR_INTERNAL, "entry in a padding row tile");
-                            // the placement XORs low bits with a function of bits it leaves
-                            // unchanged, so it is its own inverse
-                            const uint32_t logical = lds_swizzle(sidx, op.swz);
+                            const uint32_t logical = sidx;
                             const int pos = (int)(logical / kTileSlots), off = (int)(logical % kTileSlots);
                             if (pos >= nt) return fail(XCT_ERR_INTERNAL, "slot outside its stage");
                             const int rco = rcoord[rt];

@@ -19,10 +19,6 @@ constexpr int kTileSlots = 64;
 // ELL entries are stored in groups of kGroup consecutive steps per lane so
 // one lane reads a group with a single wide load.
 constexpr int kGroup = 4;
-// LDS bytes reserved after the staged rows (the SpMM's claim counters,
-// used with 16-bit operands).
-constexpr int lds_reserve(int value_dtype) { return value_dtype == XCT_F32 ? 0 : 256; }
-
 // One operator (A or A^T) in staged-ELL form.
 //
 // Output rows are grouped in tiles of 64 (one wavefront); W consecutive row
@@ -34,8 +30,8 @@ constexpr int lds_reserve(int value_dtype) { return value_dtype == XCT_F32 ? 0 :
 // so slab[blk_stage[b]*W + w*nst_b + s] .. [+1] bounds the groups of (s, w)
 // in block b (nst_b stages) and a wave's slabs are one contiguous stream.
 // Entry (group g, lane l, step q) lives at index (g*64 + l)*kGroup + q and
-// holds the stage-local slot (tile position * 64 + offset in tile, placed by
-// lds_swizzle) and the length.
+// holds the stage-local slot (tile position * 64 + offset in tile: the row of
+// the staged input in LDS) and the length.
 struct OpPlan {
     int which = 0;  // 0: A (projection), 1: A^T (backprojection)
     int64_t n_row_tiles = 0;
@@ -43,7 +39,6 @@ struct OpPlan {
     int W = 0;  // row tiles (wavefronts) per block
     int T = 0;  // input tiles per stage
     int n_blocks = 0;
-    int swz = 0;    // lds_swizzle parameter used for the stored slots
     int lanes = 0;  // lane_slot order of the rows within a row tile
     int64_t n_stages = 0;
     int64_t n_groups = 0;
@@ -67,39 +62,10 @@ struct OpPlan {
     int64_t n_slabs = 0, balanced = 0;  // (stage, wavefront) slabs; those reordered against bank conflicts
 };
 
-// LDS row placement of the staged input (a tuning option).  A stage holds
-// T*64 rows of F*elem bytes; with L = 2^k rows per 256-byte LDS line the
-// XOR variants place the row of slot s at s ^ ((s >> k) & (L-1)) ^
-// ((s >> 2k) & (L-1)) (two-term), a permutation within aligned groups of L
-// rows that spreads neighbouring voxels over the banks.  By default rows are
-// placed plainly (row = slot): the builder's slab schedule already makes the
-// reads of each LDS phase conflict-free.  Entries store the placed
-// (physical) slot.  Each map XORs the low k bits with a function of higher
-// bits it leaves unchanged, so it is its own inverse.
-// swz packs k (low 8 bits) and a variant (bits 8..15): 0 plain placement
-// (default), 1 the two-term XOR above, 2 a three-term XOR (bits k.., 2k..,
-// 3k..), 3 a one-term XOR (bits k.. only).
-__host__ __device__ inline uint32_t lds_swizzle(uint32_t s, int swz) {
-    const int k = swz & 0xff, mode = (swz >> 8) & 0xff;
-    if (k <= 0 || mode == 0) return s;
-    const uint32_t m = (1u << k) - 1u;
-    uint32_t x = s ^ ((s >> k) & m);
-    if (mode != 3) x ^= (s >> (2 * k)) & m;
-    if (mode == 2) x ^= (s >> (3 * k)) & m;
-    return x;
-}
 // Lane -> slot of the row tile: 0 row-major (lane = slot), 1 transposed.
 __host__ __device__ inline int lane_slot(int lane, int order) {
     return order ? (((lane & 7) << 3) | (lane >> 3)) : lane;
 }
-// k for rows of row_bytes bytes (0 when a row fills a line or is below 16 B).
-inline int lds_swizzle_bits(int row_bytes) {
-    if (row_bytes < 16 || row_bytes >= 256) return 0;
-    int k = 0;
-    while ((row_bytes << (k + 1)) <= 256) ++k;
-    return k;
-}
-
 // Geometry of one tiled 2D grid (H rows x Wd columns).
 struct Grid {
     int H = 0, Wd = 0;

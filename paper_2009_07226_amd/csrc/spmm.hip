@@ -100,7 +100,7 @@ struct SpmmArgs {
     const float *scale;
     double *sq_partial;
     int64_t n_row_tiles;
-    int n_blocks, T, remap, swz, lanes;
+    int n_blocks, T, remap, lanes;
 };
 
 // One group: kGroup consecutive ELL steps of one lane.
@@ -163,35 +163,11 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const char *const
     }
 }
 
-// One 16-byte-per-lane copy from global memory straight into LDS: lane l's
-// 16 bytes at g land at LDS byte lds_addr + 16 l (lds_addr wave-uniform).
-// Written as inline asm: the compiler does not count it in its vmcnt waits
-// (waits it derives are then only ever stricter), and the copy loop waits
-// for it explicitly.  M0 carries the LDS address and is restored.  No memory
-// clobber (which would turn the read-only metadata loads into vector loads
-// with full waits): the asm is volatile and sits between the stage barriers,
-// which order every LDS access around it.
-__device__ __forceinline__ void copy_to_lds16(const void *g, uint32_t lds_addr) {
-    uint32_t saved;
-    asm volatile(
-        "s_mov_b32 %0, m0\n\t"
-        "s_mov_b32 m0, %1\n\t"
-        "s_nop 0\n\t"
-        "global_load_lds_dwordx4 %2, off\n\t"
-        "s_nop 0\n\t"
-        "s_mov_b32 m0, %0"
-        : "=&s"(saved)
-        : "s"(lds_addr), "v"(g));
-}
-
-// Wait until no vector-memory operation of this wavefront is outstanding
-// (asm without a memory clobber, for the same reason as above).
-__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)"); }
-
-// Scalar loads of wave-uniform metadata (p wave-uniform).  Once a loop holds
-// inline asm, the compiler no longer proves these read-only arrays unwritten
-// and turns plain loads of them into vector loads followed by full vmcnt
-// waits; these stay on the scalar unit.
+// Scalar loads of wave-uniform metadata (p wave-uniform).  Once the stage
+// loop holds the global-to-LDS copy (which the compiler treats as a write to
+// memory), it no longer proves these read-only arrays unwritten and turns
+// plain loads of them into vector loads followed by full vmcnt waits, which
+// would drain the entry ring; these stay on the scalar unit.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ i32x4 sload_x4(const void *p) {
     i32x4 v;
@@ -252,8 +228,8 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     for (int f = 0; f < F; ++f) acc[f] = 0.f;
 
     constexpr int kVecPerTile = kTileSlots * R::RB / 16;  // 16-byte vectors per staged tile
-    // FP32 stages are copied with LDS DMA (16-bit ones by claimed chunks)
-    constexpr bool kDma = FMT == XCT_F32 && R::RB >= 16;
+    // stages of rows of 16 bytes or more are copied straight into LDS
+    constexpr bool kDma = R::RB >= 16;
     const int s0 = a.blk_stage[b], s1 = a.blk_stage[b + 1];
     const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
     const u32x4 *xin = (const u32x4 *)a.xin;
@@ -286,7 +262,8 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
 
     // Copy of one stage into LDS.  Vector c (16 bytes) of a stage that starts
     // at tile-list position q0 comes from tile tile_list[q0 + c / kVecPerTile]
-    // and goes to the placed row of its slot.
+    // and goes to the placed row of its slot (rows of 16 bytes or more are
+    // placed plainly, so whole tiles land contiguously).
     auto copy_static = [&](int q0, int nt) {
         if constexpr (kDma) {
             // Rows placed plainly: a tile's rows are contiguous in LDS, so each
@@ -316,30 +293,6 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
                 }
             }
             __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's pieces are in LDS
-        } else if constexpr (R::RB >= 16) {
-            // A tile is a multiple of 64 vectors, so the tile of each copied
-            // vector is wave-uniform (a scalar load); all loads of a batch are
-            // issued before their stores.
-            constexpr int kBatch = 10;
-            const int total = nt * kVecPerTile;
-            for (int base = 0; base < total; base += kBatch * nthr) {
-                u32x4 v[kBatch];
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) {
-                    const int e2 = min(base + k * nthr + tid, total - 1);
-                    const int q = __builtin_amdgcn_readfirstlane(e2 / kVecPerTile);
-                    v[k] = xin[(int64_t)a.tile_list[q0 + q] * kVecPerTile + e2 % kVecPerTile];
-                }
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) {
-                    const int e2 = base + k * nthr + tid;
-                    if (e2 < total) {
-                        const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
-                        const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
-                        ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v[k];
-                    }
-                }
-            }
         } else {
             for (int e2 = tid; e2 < nt * kVecPerTile; e2 += nthr) {
                 const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
@@ -348,7 +301,7 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
                 const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int k = 0; k < per; ++k) {
-                    const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r * per + k), a.swz);
+                    const uint32_t slot = (uint32_t)(q * kTileSlots + r * per + k);
                     char *dst = smem + slot * R::RB;
                     if constexpr (R::RB == 8) {
                         *(u32x2 *)dst = u32x2{u[2 * k], u[2 * k + 1]};
@@ -362,17 +315,6 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
         }
     };
 
-    // 16-bit operands: the next stage's copy is claimed chunk by chunk by
-    // the waves that finish first (below); two claim counters follow the
-    // stage buffer, one per stage parity.  FP32 rows make the stage loop
-    // bound by LDS bandwidth, where early loads gain nothing, so FP32 keeps
-    // the plain copy between two barriers.
-    constexpr bool kClaimed = FMT != XCT_F32 && R::RB >= 16;
-    int *claim = (int *)(smem + (size_t)a.T * kTileSlots * R::RB);
-    if (kClaimed && tid == 0) {
-        claim[0] = 0;
-        claim[1] = 0;
-    }
     if (s0 < s1) copy_static(t0, min(a.T, t1 - t0));
     __syncthreads();
 
@@ -405,52 +347,8 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
         if (s + 1 < s1) {
             const int q0n = t0 + (s + 1 - s0) * a.T;
             const int ntn = min(a.T, t1 - q0n);
-            if constexpr (kClaimed) {
-                // The next stage's copy is split in chunks of 64 vectors that
-                // waves claim as they finish this stage: early waves load them
-                // while the slow ones still compute, so the copy leaves the
-                // critical path.  Data is stored once every wave is done.
-                constexpr int kClaim = 12;
-                const int chunks = ntn * kVecPerTile / 64;
-                const int par = (s - s0) & 1;
-                int c0 = 0;
-                if (lane == 0) c0 = atomicAdd(&claim[par], kClaim);
-                c0 = __builtin_amdgcn_readfirstlane(__shfl(c0, 0, 64));
-                const int cn = max(0, min(kClaim, chunks - c0));
-                u32x4 v[kClaim];
-                if (cn > 0) {
-                    // one branch around unconditional loads (a partial claim
-                    // re-reads its last chunk), so the loads stay in flight together
-#pragma unroll
-                    for (int k = 0; k < kClaim; ++k) {
-                        const int c = c0 + min(k, cn - 1);
-                        const int q = c * 64 / kVecPerTile;
-                        v[k] = xin[(int64_t)a.tile_list[q0n + q] * kVecPerTile + (c * 64) % kVecPerTile + lane];
-                    }
-                }
-                __syncthreads();  // every wave is done with this stage's data
-                if (tid == 0) claim[par] = 0;  // reused two stages later
-#pragma unroll
-                for (int k = 0; k < kClaim; ++k) {
-                    if (k < cn) {
-                        const int e2 = (c0 + k) * 64 + lane;
-                        const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
-                        const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
-                        ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = v[k];
-                    }
-                }
-                // chunks nobody claimed (only when a stage has more than W*kClaim)
-                for (int c = W * kClaim + wave; c < chunks; c += W) {
-                    const int e2 = c * 64 + lane;
-                    const int q = e2 / kVecPerTile, r = e2 % kVecPerTile;
-                    const u32x4 w = xin[(int64_t)a.tile_list[q0n + q] * kVecPerTile + r];
-                    const uint32_t slot = lds_swizzle((uint32_t)(q * kTileSlots + r / R::CH), a.swz);
-                    ((u32x4 *)smem)[slot * R::CH + (r % R::CH)] = w;
-                }
-            } else {
-                __syncthreads();
-                copy_static(q0n, ntn);
-            }
+            __syncthreads();  // every wave is done with this stage's data
+            copy_static(q0n, ntn);
             __syncthreads();  // next stage in place
         }
     }
@@ -529,10 +427,9 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.n_blocks = op.n_blocks;
     a.T = op.T;
     a.remap = L.remap;
-    a.swz = op.swz;
     a.lanes = op.lanes;
     typedef typename Stor<FMT>::T XT;
-    size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT) + lds_reserve(FMT);
+    size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
     const size_t red = sizeof(double) * (size_t)op.W * F;
     if (smem < red) smem = red;
     static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far

@@ -100,10 +100,9 @@ def test_project_backproject_parity(N, M, C, B):
 
 
 @pytest.mark.parametrize("opts", [dict(stage_order=1), dict(tile_waves=4, lds_bytes=32768),
-                                  dict(tile_waves=16, xcd_remap=-1), dict(fuse=4), dict(lds_layout=1),
-                                  dict(lds_layout=2, lane_order=1), dict(lds_layout=3, tile_waves=16,
-                                                                        lds_bytes=163840),
-                                  dict(slab_order=1), dict(fuse=8), dict(fuse=8, lds_layout=1)])
+                                  dict(tile_waves=16, xcd_remap=-1), dict(fuse=4), dict(fuse=2),
+                                  dict(lane_order=1), dict(tile_waves=16, lds_bytes=163840),
+                                  dict(slab_order=1), dict(fuse=8), dict(fuse=8, lane_order=1)])
 def test_plan_options_keep_parity(opts):
     N, M, C, B = 64, 90, 64, 5
     A = gpu_matrix(N, M, C, **opts)
