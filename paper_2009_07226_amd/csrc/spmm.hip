@@ -73,18 +73,41 @@ __device__ __forceinline__ void expand(const u32x4 w, float (&x)[SPC]) {
     }
 }
 
+// LDS addresses are 32-bit byte offsets into the workgroup's LDS.
+#define XCT_LDS __attribute__((address_space(3)))
+template <class T> __device__ __forceinline__ const XCT_LDS T *lds_ptr(uint32_t addr) {
+    return (const XCT_LDS T *)(uintptr_t)addr;
+}
+__device__ __forceinline__ uint32_t lds_addr(const char *generic_smem) {
+    return (uint32_t)(uintptr_t)(XCT_LDS const char *)generic_smem;
+}
+
+// Address of a staged row's chunk: slot * RB + cb, the slot being the low
+// (HI = false) or high half of `packed`.  One v_mad_u32_u16 whose operand
+// select picks the half, so extracting the slot costs nothing.
+template <int RB, bool HI>
+__device__ __forceinline__ uint32_t row_addr(uint32_t packed, uint32_t cb) {
+    static_assert(RB > 0 && RB <= 64, "RB must be an inline constant");
+    uint32_t r;
+    if constexpr (HI)
+        asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(packed), "i"(RB), "v"(cb));
+    else
+        asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(packed), "i"(RB), "v"(cb));
+    return r;
+}
+
 // Load a row of fewer than 16 bytes.
 template <int RB>
-__device__ __forceinline__ u32x4 load_small(const char *p) {
+__device__ __forceinline__ u32x4 load_small(uint32_t addr) {
     u32x4 w = {0u, 0u, 0u, 0u};
     if constexpr (RB == 8) {
-        const u32x2 v = *(const u32x2 *)p;
+        const u32x2 v = *lds_ptr<u32x2>(addr);
         w.x = v.x;
         w.y = v.y;
     } else if constexpr (RB == 4) {
-        w.x = *(const uint32_t *)p;
+        w.x = *lds_ptr<uint32_t>(addr);
     } else {
-        w.x = *(const uint16_t *)p;
+        w.x = *lds_ptr<uint16_t>(addr);
     }
     return w;
 }
@@ -109,30 +132,39 @@ template <> struct Group<XCT_F32> { u32x2 s; f32x4 v; };
 template <> struct Group<XCT_F16> { u32x4 p; };
 template <> struct Group<XCT_BF16> { u32x4 p; };
 
-// Group gi of lane `lane` (entry layout: see OpPlan).
+// Bytes of one group (64 lanes x kGroup entries; layout: see OpPlan).
+template <int FMT> struct GroupBytes { static constexpr int value = 1024; };
+template <> struct GroupBytes<XCT_F32> { static constexpr int value = 1536; };
+
+// Lane `lane`'s part of group g of a wavefront's entry stream, read through
+// a buffer descriptor of the stream: the group offset is a scalar operand, so
+// the address arithmetic costs no vector instructions.  Streamed once:
+// non-temporal.
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
+constexpr int kNonTemporal = 2;
 template <int FMT>
-__device__ __forceinline__ Group<FMT> load_group(const SpmmArgs &a, int64_t gi, int lane) {
-    Group<FMT> g;
+__device__ __forceinline__ Group<FMT> load_group(__amdgpu_buffer_rsrc_t rs, int g, int lane) {
+    Group<FMT> r;
+    const int so = g * GroupBytes<FMT>::value;
     if constexpr (FMT == XCT_F32) {
-        g.s = __builtin_nontemporal_load((const u32x2 *)a.slot + gi * 192 + lane);
-        g.v = __builtin_nontemporal_load((const f32x4 *)a.val + gi * 96 + 32 + lane);
+        r.s = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, so, kNonTemporal));
+        r.v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 512 + lane * 16, so, kNonTemporal));
     } else {
-        g.p = __builtin_nontemporal_load((const u32x4 *)a.packed + gi * kTileSlots + lane);
+        r.p = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, so, kNonTemporal));
     }
-    return g;
+    return r;
 }
 
 template <int FMT, int F>
-__device__ __forceinline__ void use_group(const Group<FMT> &g, const char *const (&cbase)[RowShape<FMT, F>::CH],
+__device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&cb)[RowShape<FMT, F>::CH],
                                           float (&acc)[F]) {
     typedef RowShape<FMT, F> R;
-    uint32_t sl[kGroup];
+    // the word holding step q's slot, and whether it is the high half
+    uint32_t sw[kGroup];
     float v[kGroup];
     if constexpr (FMT == XCT_F32) {
-        sl[0] = g.s.x & 0xffffu;
-        sl[1] = g.s.x >> 16;
-        sl[2] = g.s.y & 0xffffu;
-        sl[3] = g.s.y >> 16;
+        sw[0] = sw[1] = g.s.x;
+        sw[2] = sw[3] = g.s.y;
         v[0] = g.v.x;
         v[1] = g.v.y;
         v[2] = g.v.z;
@@ -141,22 +173,33 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const char *const
         const uint32_t p[4] = {g.p.x, g.p.y, g.p.z, g.p.w};
 #pragma unroll
         for (int q = 0; q < kGroup; ++q) {
-            sl[q] = p[q] >> 16;
+            sw[q] = p[q];
             v[q] = FMT == XCT_F16 ? h16_to_f32(p[q] & 0xffffu) : bf16_to_f32(p[q] & 0xffffu);
         }
     }
+    // all of the group's LDS reads are issued before its FMAs, so a
+    // wavefront waits for LDS latency once per group
+    u32x4 w[kGroup][R::CH];
 #pragma unroll
     for (int q = 0; q < kGroup; ++q) {
-        const uint32_t roff = sl[q] * R::RB;
+        constexpr bool kHiAlways = FMT != XCT_F32;  // 16-bit entries: slot << 16 | value
 #pragma unroll
         for (int j = 0; j < R::CH; ++j) {
-            u32x4 w;
+            const uint32_t ad = (kHiAlways || (q & 1)) ? row_addr<R::RB, true>(sw[q], cb[j])
+                                                        : row_addr<R::RB, false>(sw[q], cb[j]);
             if constexpr (R::RB >= 16)
-                w = *(const u32x4 *)(cbase[j] + roff);
+                w[q][j] = *lds_ptr<u32x4>(ad);
             else
-                w = load_small<R::RB>(cbase[0] + roff);
+                w[q][j] = load_small<R::RB>(ad);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the FMAs
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+#pragma unroll
+        for (int j = 0; j < R::CH; ++j) {
             float x[R::SPC];
-            expand<FMT, R::SPC>(w, x);
+            expand<FMT, R::SPC>(w[q][j], x);
 #pragma unroll
             for (int t = 0; t < R::SPC; ++t) acc[j * R::SPC + t] = fmaf(v[q], x[t], acc[j * R::SPC + t]);
         }
@@ -199,7 +242,7 @@ template <int FMT> struct RingDepth { static constexpr int value = 6; };
 template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
 
 template <int FMT, int F>
-__global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spmm(SpmmArgs a) {
     typedef RowShape<FMT, F> R;
     constexpr int D = RingDepth<FMT>::value;
     extern __shared__ __align__(16) char smem[];
@@ -217,11 +260,11 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     // of one LDS cycle spread over the chunks; accumulator block j holds the
     // slices of that rotated chunk.
     int coff[R::CH];
-    const char *cbase[R::CH];  // LDS address of this lane's chunk j of row 0
+    uint32_t cb[R::CH];  // LDS address of this lane's chunk j of row 0
 #pragma unroll
     for (int j = 0; j < R::CH; ++j) {
         coff[j] = ((j + lane) & (R::CH - 1)) * 16;
-        cbase[j] = smem + coff[j];
+        cb[j] = lds_addr(smem) + coff[j];
     }
     float acc[F];
 #pragma unroll
@@ -239,24 +282,34 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
     const int nst = s1 - s0;
     const int64_t p0 = (int64_t)s0 * W + (int64_t)wave * nst;
     const int64_t gw = a.slab[p0], ge = a.slab[p0 + nst];
-    int64_t lg = gw;  // next group to load
+    // Group indices below are relative to the wave's first group (a wave's
+    // stream is far below 2^31 bytes).  Past the end of the stream the last
+    // group is re-read; an empty stream re-reads the group before it, or
+    // group 0 (the builder allocates at least one group).
+    constexpr int GB = GroupBytes<FMT>::value;
+    const int ne = (int)(ge - gw);
+    const int64_t gfirst = ne > 0 ? gw : (gw > 0 ? gw - 1 : 0);
+    const char *ent_w =
+        (const char *)(FMT == XCT_F32 ? (const void *)a.slot : (const void *)a.packed) + gfirst * GB;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)ent_w, (short)0, (ne > 0 ? ne : 1) * GB, kRsrcWord3);
+    const int rlast = ne > 0 ? ne - 1 : 0;
+    int lg = 0;  // next group to load
     // Slot d of the ring holds group sg[d].  Every visit of a slot reloads it
     // unconditionally (a slot that was not consumed reloads the group it
-    // already holds; past the end of the stream the last group is re-read),
-    // so each ring register is only ever the direct target of its own load:
-    // no register copies and no waits beyond the oldest load.
-    // (group 0 always exists: the builder allocates at least one group)
-    auto take = [&]() -> int64_t {
-        const int64_t g = lg < ge ? lg : (ge > 0 ? ge - 1 : 0);
+    // already holds), so each ring register is only ever the direct target
+    // of its own load: no register copies and no waits beyond the oldest load.
+    auto take = [&]() -> int {
+        const int g = lg < ne ? lg : rlast;
         ++lg;
         return g;
     };
     Group<FMT> e[D];
-    int64_t sg[D];
+    int sg[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         sg[d] = take();
-        e[d] = load_group<FMT>(a, sg[d], lane);
+        e[d] = load_group<FMT>(rs, sg[d], lane);
     }
     int ph = 0;  // ring slot holding the next group
 
@@ -335,10 +388,10 @@ __global__ void __launch_bounds__(1024) k_spmm(SpmmArgs a) {
             for (int d = 0; d < D; ++d) {
                 const int k = i + d;
                 if (k >= 0 && k < n) {
-                    use_group<FMT, F>(e[d], cbase, acc);
+                    use_group<FMT, F>(e[d], cb, acc);
                     sg[d] = take();
                 }
-                e[d] = load_group<FMT>(a, sg[d], lane);
+                e[d] = load_group<FMT>(rs, sg[d], lane);
             }
         }
         ph = (ph + n) % D;
