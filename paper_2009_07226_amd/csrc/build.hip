@@ -189,6 +189,13 @@ struct StageOrder {
 
 // ---- builder kernels --------------------------------------------------------
 
+// Slab of (stage s, row tile h * P + w) in a block whose stages start at sb:
+// wavefront w's slabs are contiguous, stage by stage, its R row tiles
+// interleaved within each stage, so a wavefront's entries are one stream.
+__host__ __device__ __forceinline__ int64_t slab_index(int64_t sb, int nst, int W, int R, int w, int h, int s) {
+    return sb * W + ((int64_t)w * nst + s) * R + h;
+}
+
 struct BuildLds {
     uint32_t *bits;    // [nwords] touched input tiles, by rank
     uint32_t *prefix;  // [nwords] set bits before each word
@@ -209,16 +216,19 @@ __device__ __forceinline__ BuildLds carve(void *smem, int nwords, int nthr) {
     return L;
 }
 
+// A block has W row tiles; its P = blockDim / 64 wavefronts take R = W / P
+// each: wavefront w holds row tiles h * P + w, h < R.
 template <class Rows>
 __device__ void mark_tiles(const Rows &rows, const int32_t *key_of, int64_t n_row_tiles, const BuildLds &L,
-                           int nwords, int64_t *entries) {
+                           int nwords, int64_t *entries, int W) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int w = tid; w < nwords; w += nthr) L.bits[w] = 0u;
     __syncthreads();
-    const int W = nthr >> 6;
-    const int64_t rt = (int64_t)blockIdx.x * W + (tid >> 6);
+    const int P = nthr >> 6, R = W / P;
     int64_t n = 0;
-    if (rt < n_row_tiles) {
+    for (int h = 0; h < R; ++h) {
+        const int64_t rt = (int64_t)blockIdx.x * W + h * P + (tid >> 6);
+        if (rt >= n_row_tiles) continue;
         int last = -1;
         rows.run(rt, tid & 63, key_of, [&](int key, int, double) {
             ++n;
@@ -280,12 +290,12 @@ __device__ __forceinline__ int tile_pos(const BuildLds &L, int rank) {
 }
 
 template <class Rows>
-__global__ void k_footprint(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int32_t *ntiles,
+__global__ void k_footprint(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int W, int32_t *ntiles,
                             int64_t *nnz) {
     extern __shared__ __align__(16) char smem[];
     const BuildLds L = carve(smem, nwords, blockDim.x);
     int64_t e = 0;
-    mark_tiles(rows, ord.key_of + ord.base(blockIdx.x), n_row_tiles, L, nwords, &e);
+    mark_tiles(rows, ord.key_of + ord.base(blockIdx.x), n_row_tiles, L, nwords, &e, W);
     int64_t t = 0;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) t += __popc(L.bits[w]);
     const int64_t tiles = block_sum(L, t);
@@ -302,16 +312,17 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 template <class Rows>
-__global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW,
+__global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int W, int T, int SW,
                        const int32_t *blk_tile, const int32_t *blk_stage, int32_t *tile_list, int32_t *stage_len,
                        int *err) {
     extern __shared__ __align__(16) char smem[];
-    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6;
+    const int tid = threadIdx.x, nthr = blockDim.x, P = nthr >> 6, R = W / P, wave = tid >> 6;
+    const int NV = W * kTileSlots;  // row lanes of the block (counters per stage)
     const BuildLds L = carve(smem, nwords, nthr);
     const int b = blockIdx.x;
     const int32_t *key_of = ord.key_of + ord.base(b);
     const int32_t *tile_of = ord.tile_of + ord.base(b);
-    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr);
+    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr, W);
     build_prefix(L, nwords);
     const int base = blk_tile[b];
     const int ntl = blk_tile[b + 1] - base;
@@ -329,44 +340,50 @@ __global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
         }
     }
     const int nst = blk_stage[b + 1] - blk_stage[b];
-    const int64_t rt = (int64_t)b * W + wave;
     for (int s0 = 0; s0 < nst; s0 += SW) {
-        for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
+        for (int q = tid; q < SW * NV; q += nthr) L.cnt[q] = 0;
         __syncthreads();
-        if (rt < n_row_tiles) {
+        for (int h = 0; h < R; ++h) {
+            const int64_t rt = (int64_t)b * W + h * P + wave;
+            const int vt = h * nthr + tid;
+            if (rt >= n_row_tiles) continue;
             rows.run(rt, tid & 63, key_of, [&](int key, int, double) {
                 const int st = tile_pos(L, key) / T - s0;
-                if (st >= 0 && st < SW && s0 + st < nst) L.cnt[st * nthr + tid] += 1;
+                if (st >= 0 && st < SW && s0 + st < nst) L.cnt[st * NV + vt] += 1;
             });
         }
         __syncthreads();
         const int lim = min(SW, nst - s0);
-        for (int st = 0; st < lim; ++st) {
-            const int v = wave_max((int)L.cnt[st * nthr + tid]);
-            if ((tid & 63) == 0)
-                stage_len[(int64_t)(blk_stage[b] + s0 + st) * W + wave] = (v + kGroup - 1) / kGroup;
-        }
+        for (int st = 0; st < lim; ++st)
+            for (int h = 0; h < R; ++h) {
+                const int v = wave_max((int)L.cnt[st * NV + h * nthr + tid]);
+                if ((tid & 63) == 0)
+                    stage_len[(int64_t)(blk_stage[b] + s0 + st) * W + h * P + wave] = (v + kGroup - 1) / kGroup;
+            }
         __syncthreads();
     }
 }
 
 template <class Rows, int FMT>
-__global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int T, int SW,
+__global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int W, int T, int SW,
                        const int32_t *blk_stage, const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed,
                        int *err) {
     extern __shared__ __align__(16) char smem[];
-    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, nthr = blockDim.x, P = nthr >> 6, R = W / P, wave = tid >> 6, lane = tid & 63;
+    const int NV = W * kTileSlots;
     const BuildLds L = carve(smem, nwords, nthr);
     const int b = blockIdx.x;
     const int32_t *key_of = ord.key_of + ord.base(b);
-    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr);
+    mark_tiles(rows, key_of, n_row_tiles, L, nwords, nullptr, W);
     build_prefix(L, nwords);
     const int nst = blk_stage[b + 1] - blk_stage[b];
-    const int64_t rt = (int64_t)b * W + wave;
     for (int s0 = 0; s0 < nst; s0 += SW) {
-        for (int q = tid; q < SW * nthr; q += nthr) L.cnt[q] = 0;
+        for (int q = tid; q < SW * NV; q += nthr) L.cnt[q] = 0;
         __syncthreads();
-        if (rt < n_row_tiles) {
+        for (int h = 0; h < R; ++h) {
+            const int64_t rt = (int64_t)b * W + h * P + wave;
+            const int vt = h * nthr + tid;
+            if (rt >= n_row_tiles) continue;
             rows.run(rt, lane, key_of, [&](int key, int off, double len) {
                 const int pos = tile_pos(L, key);
                 const int st = pos / T;
@@ -376,8 +393,8 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
                     atomicOr(err, 4);
                     return;
                 }
-                const int n = L.cnt[sl * nthr + tid]++;
-                const int64_t gs = (int64_t)blk_stage[b] * W + (int64_t)wave * nst + st;
+                const int n = L.cnt[sl * NV + vt]++;
+                const int64_t gs = slab_index(blk_stage[b], nst, W, R, wave, h, st);
                 const int64_t g = slab[gs] + n / kGroup;
                 if (g >= slab[gs + 1]) {
                     atomicOr(err, 1);
@@ -802,20 +819,23 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     op.n_row_tiles = n_row_tiles;
     op.n_in_tiles = n_in_tiles;
     op.W = W;
+    op.R = W > 16 ? W / 16 : 1;  // row tiles per wavefront
     op.T = T;
     op.n_blocks = (int)((n_row_tiles + W - 1) / W);
-    const int nthr = W * kTileSlots;
+    const int R = op.R, P = W / R;
+    const int nthr = P * kTileSlots;  // threads of the builder kernels: one per lane of a wavefront
+    const int NV = W * kTileSlots;    // row lanes of a block
     const int nwords = (int)((n_in_tiles + 31) / 32);
     int dev = 0;
     XCT_HIP_TRY(hipGetDevice(&dev));
     int lds_max = 0;
     XCT_HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t fixed = sizeof(int64_t) * (size_t)(nthr + 1) + sizeof(uint32_t) * 2 * (size_t)nwords;
-    if ((size_t)lds_max < fixed + sizeof(uint16_t) * (size_t)nthr)
+    if ((size_t)lds_max < fixed + sizeof(uint16_t) * (size_t)NV)
         return fail(XCT_ERR_UNSUPPORTED, "grid too large for the builder's LDS tile bitmap");
-    int SW = (int)std::min<size_t>(64, ((size_t)lds_max - fixed) / (sizeof(uint16_t) * (size_t)nthr));
+    int SW = (int)std::min<size_t>(64, ((size_t)lds_max - fixed) / (sizeof(uint16_t) * (size_t)NV));
     const size_t smem_mark = fixed;
-    const size_t smem_win = fixed + sizeof(uint16_t) * (size_t)SW * nthr;
+    const size_t smem_win = fixed + sizeof(uint16_t) * (size_t)SW * NV;
 
     const int nb = op.n_blocks;
     DevBuf d_nt, d_nnz, d_len, d_err;
@@ -823,7 +843,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     XCT_HIP_TRY(hipMalloc(&d_nnz.p, sizeof(int64_t) * nb));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_footprint<Rows>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_mark));
-    hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, ord, n_row_tiles, nwords,
+    hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, ord, n_row_tiles, nwords, W,
                        (int32_t *)d_nt.p, (int64_t *)d_nnz.p);
     XCT_HIP_TRY(hipGetLastError());
     std::vector<int32_t> nt(nb);
@@ -858,25 +878,27 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     XCT_HIP_TRY(hipMemsetAsync(d_err.p, 0, sizeof(int), st));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_plan<Rows>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)smem_win));
-    hipLaunchKernelGGL(k_plan<Rows>, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW,
+    hipLaunchKernelGGL(k_plan<Rows>, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, W, T, SW,
                        op.blk_tile, op.blk_stage, op.tile_list, (int32_t *)d_len.p, (int *)d_err.p);
     XCT_HIP_TRY(hipGetLastError());
     std::vector<int32_t> len(nlen);
     if (nlen) XCT_HIP_TRY(hipMemcpyAsync(len.data(), d_len.p, sizeof(int32_t) * nlen, hipMemcpyDeviceToHost, st));
     XCT_HIP_TRY(hipStreamSynchronize(st));
-    // Slabs are laid out wave by wave within a block, each wave's stages in
-    // order, so a wave's entries form one contiguous stream:
-    // slab[blk_stage[b]*W + w*nst_b + s] is the first group of (stage s, wave w).
+    // Slabs are laid out wavefront by wavefront within a block (slab_index),
+    // so a wavefront's entries form one contiguous stream; len is indexed
+    // [stage][row tile of the block].
     std::vector<int64_t> slab(nlen + 1, 0);
     {
         int64_t acc = 0;
         for (int b = 0; b < nb; ++b) {
             const int sb = blk_stage[b], nst = blk_stage[b + 1] - blk_stage[b];
-            for (int w = 0; w < W; ++w)
-                for (int sl = 0; sl < nst; ++sl) {
-                    slab[(int64_t)sb * W + (int64_t)w * nst + sl] = acc;
-                    acc += len[(int64_t)(sb + sl) * W + w];
-                }
+            for (int w = 0; w < P; ++w)
+                for (int sl = 0; sl < nst; ++sl)
+                    for (int h = 0; h < R; ++h) {
+                        const int64_t i = slab_index(sb, nst, W, R, w, h, sl);
+                        slab[i] = acc;
+                        acc += len[(int64_t)(sb + sl) * W + h * P + w];
+                    }
         }
         slab[nlen] = acc;
     }
@@ -898,7 +920,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     auto fill = [&](auto kern) -> int {
         XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem_win));
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, T, SW,
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, W, T, SW,
                            op.blk_stage, op.slab, op.slot, op.val, op.packed, (int *)d_err.p);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
@@ -1010,7 +1032,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     const int W = o.tile_waves ? o.tile_waves : 16;
     const int F = o.fuse ? o.fuse : 16;
     int lds = o.lds_bytes;
-    if (W < 1 || W > 16) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16]");
+    if (W < 1 || (W > 16 && W != 32)) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16] or 32");
     if (F != 1 && F != 2 && F != 4 && F != 8 && F != 16) return fail(XCT_ERR_INVALID, "fuse must be 1, 2, 4, 8 or 16");
     const int per_tile = kTileSlots * F * elem_bytes(value_dtype);
     int dev = 0;
@@ -1163,7 +1185,8 @@ extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, 
             const int nst = blk_stage[b + 1] - blk_stage[b];
             for (int w = 0; w < W; ++w) {
                 const int64_t rt = (int64_t)b * W + w;
-                const int64_t p = (int64_t)blk_stage[b] * W + (int64_t)w * nst + sl;
+                const int P = W / op.R;
+                const int64_t p = slab_index(blk_stage[b], nst, W, op.R, w % P, w / P, sl);
                 for (int64_t g = slab[p]; g < slab[p + 1]; ++g) {
                     for (int lane = 0; lane < kTileSlots; ++lane) {
                         for (int q = 0; q < kGroup; ++q) {

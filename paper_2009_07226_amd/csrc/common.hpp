@@ -21,14 +21,17 @@ constexpr int kTileSlots = 64;
 constexpr int kGroup = 4;
 // One operator (A or A^T) in staged-ELL form.
 //
-// Output rows are grouped in tiles of 64 (one wavefront); W consecutive row
-// tiles in Hilbert order make one workgroup ("block").  The input tiles a
-// block touches, in its staging order, form its tile list; the list is cut
-// into stages of at most T tiles, each loaded into LDS in turn.  For stage s
-// and wave w the entries of the wave's 64 rows that fall in the stage form
-// one ELL slab; slabs are stored wave by wave (each wave's stages in order),
-// so slab[blk_stage[b]*W + w*nst_b + s] .. [+1] bounds the groups of (s, w)
-// in block b (nst_b stages) and a wave's slabs are one contiguous stream.
+// Output rows are grouped in tiles of 64 (one wavefront of lanes); W
+// consecutive row tiles in Hilbert order make one workgroup ("block") of
+// P = W / R wavefronts, wavefront w holding row tiles h * P + w (h < R).  The
+// input tiles a block touches, in its staging order, form its tile list; the
+// list is cut into stages of at most T tiles, each loaded into LDS in turn.
+// For stage s and row tile the entries of its 64 rows that fall in the stage
+// form one ELL slab; slabs are stored wavefront by wavefront (each
+// wavefront's stages in order, its R row tiles interleaved per stage), so
+// slab[blk_stage[b]*W + (w*nst_b + s)*R + h] .. [+1] bounds the groups of
+// (s, h * P + w) in block b (nst_b stages) and a wavefront's slabs are one
+// contiguous stream.
 // Entry (group g, lane l, step q) lives at index (g*64 + l)*kGroup + q and
 // holds the stage-local slot (tile position * 64 + offset in tile: the row of
 // the staged input in LDS) and the length.
@@ -36,7 +39,8 @@ struct OpPlan {
     int which = 0;  // 0: A (projection), 1: A^T (backprojection)
     int64_t n_row_tiles = 0;
     int64_t n_in_tiles = 0;
-    int W = 0;  // row tiles (wavefronts) per block
+    int W = 0;  // row tiles per block
+    int R = 1;  // row tiles per wavefront (W / R wavefronts per block)
     int T = 0;  // input tiles per stage
     int n_blocks = 0;
     int lanes = 0;  // lane_slot order of the rows within a row tile

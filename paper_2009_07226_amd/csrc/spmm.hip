@@ -124,6 +124,7 @@ struct SpmmArgs {
     double *sq_partial;
     int64_t n_row_tiles;
     int n_blocks, T, remap, lanes;
+    int W;  // row tiles per block (R per wavefront)
 };
 
 // One group: kGroup consecutive ELL steps of one lane.
@@ -155,7 +156,7 @@ __device__ __forceinline__ Group<FMT> load_group(__amdgpu_buffer_rsrc_t rs, int 
     return r;
 }
 
-template <int FMT, int F>
+template <int FMT, int F, int KB>
 __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&cb)[RowShape<FMT, F>::CH],
                                           float (&acc)[F]) {
     typedef RowShape<FMT, F> R;
@@ -177,31 +178,37 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&
             v[q] = FMT == XCT_F16 ? h16_to_f32(p[q] & 0xffffu) : bf16_to_f32(p[q] & 0xffffu);
         }
     }
-    // all of the group's LDS reads are issued before its FMAs, so a
-    // wavefront waits for LDS latency once per group
-    u32x4 w[kGroup][R::CH];
+    // The LDS reads of KB steps are issued together ahead of their FMAs, so
+    // a wavefront waits for LDS latency once per KB steps.
+    static_assert(kGroup % KB == 0, "KB must divide the group");
 #pragma unroll
-    for (int q = 0; q < kGroup; ++q) {
-        constexpr bool kHiAlways = FMT != XCT_F32;  // 16-bit entries: slot << 16 | value
+    for (int q0 = 0; q0 < kGroup; q0 += KB) {
+        u32x4 w[KB][R::CH];
 #pragma unroll
-        for (int j = 0; j < R::CH; ++j) {
-            const uint32_t ad = (kHiAlways || (q & 1)) ? row_addr<R::RB, true>(sw[q], cb[j])
-                                                        : row_addr<R::RB, false>(sw[q], cb[j]);
-            if constexpr (R::RB >= 16)
-                w[q][j] = *lds_ptr<u32x4>(ad);
-            else
-                w[q][j] = load_small<R::RB>(ad);
+        for (int k = 0; k < KB; ++k) {
+            const int q = q0 + k;
+            constexpr bool kHiAlways = FMT != XCT_F32;  // 16-bit entries: slot << 16 | value
+#pragma unroll
+            for (int j = 0; j < R::CH; ++j) {
+                const uint32_t ad = (kHiAlways || (q & 1)) ? row_addr<R::RB, true>(sw[q], cb[j])
+                                                            : row_addr<R::RB, false>(sw[q], cb[j]);
+                if constexpr (R::RB >= 16)
+                    w[k][j] = *lds_ptr<u32x4>(ad);
+                else
+                    w[k][j] = load_small<R::RB>(ad);
+            }
         }
-    }
-    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the FMAs
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the FMAs
 #pragma unroll
-    for (int q = 0; q < kGroup; ++q) {
+        for (int k = 0; k < KB; ++k) {
 #pragma unroll
-        for (int j = 0; j < R::CH; ++j) {
-            float x[R::SPC];
-            expand<FMT, R::SPC>(w[q][j], x);
+            for (int j = 0; j < R::CH; ++j) {
+                float x[R::SPC];
+                expand<FMT, R::SPC>(w[k][j], x);
 #pragma unroll
-            for (int t = 0; t < R::SPC; ++t) acc[j * R::SPC + t] = fmaf(v[q], x[t], acc[j * R::SPC + t]);
+                for (int t = 0; t < R::SPC; ++t)
+                    acc[j * R::SPC + t] = fmaf(v[q0 + k], x[t], acc[j * R::SPC + t]);
+            }
         }
     }
 }
@@ -241,12 +248,19 @@ __device__ __forceinline__ void prio_for_remaining(int rem) {
 template <int FMT> struct RingDepth { static constexpr int value = 6; };
 template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
 
-template <int FMT, int F>
+// LDS reads issued together: the whole group, or half of it when a
+// wavefront holds two FP32 accumulator sets of 16 slices (register budget).
+template <int FMT, int F, int RT> struct ReadBatch { static constexpr int value = 4; };
+template <> struct ReadBatch<XCT_F32, 16, 2> { static constexpr int value = 2; };
+
+// RT: row tiles per wavefront (a.W / RT wavefronts per block).
+template <int FMT, int F, int RT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spmm(SpmmArgs a) {
     typedef RowShape<FMT, F> R;
     constexpr int D = RingDepth<FMT>::value;
+    constexpr int KB = ReadBatch<FMT, F, RT>::value;
     extern __shared__ __align__(16) char smem[];
-    const int tid = threadIdx.x, nthr = blockDim.x, W = nthr >> 6;
+    const int tid = threadIdx.x, nthr = blockDim.x, P = nthr >> 6, W = a.W;
     // wave-uniform: keeps the slab bounds and loop control in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     int b = blockIdx.x;
@@ -266,9 +280,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         coff[j] = ((j + lane) & (R::CH - 1)) * 16;
         cb[j] = lds_addr(smem) + coff[j];
     }
-    float acc[F];
+    float acc[RT][F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] = 0.f;
+    for (int h = 0; h < RT; ++h)
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[h][f] = 0.f;
 
     constexpr int kVecPerTile = kTileSlots * R::RB / 16;  // 16-byte vectors per staged tile
     // stages of rows of 16 bytes or more are copied straight into LDS
@@ -277,11 +293,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     const int t0 = a.blk_tile[b], t1 = a.blk_tile[b + 1];
     const u32x4 *xin = (const u32x4 *)a.xin;
 
-    // The wave's entries are one contiguous stream of groups [gw, ge);
-    // stage s uses slab[p0 + s - s0] .. slab[p0 + s - s0 + 1].
+    // The wave's entries are one contiguous stream of groups [gw, ge); its
+    // row tile h uses slab[p0 + (s - s0) * RT + h] .. [+1] in stage s.
     const int nst = s1 - s0;
-    const int64_t p0 = (int64_t)s0 * W + (int64_t)wave * nst;
-    const int64_t gw = a.slab[p0], ge = a.slab[p0 + nst];
+    const int64_t p0 = (int64_t)s0 * W + (int64_t)wave * nst * RT;
+    const int64_t gw = a.slab[p0], ge = a.slab[p0 + nst * RT];
     // Group indices below are relative to the wave's first group (a wave's
     // stream is far below 2^31 bytes).  Past the end of the stream the last
     // group is re-read; an empty stream re-reads the group before it, or
@@ -325,9 +341,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
             // the consecutive pieces [c0, c1); their tiles' indices come four
             // at a time (the tile list is padded by 4 entries).
             constexpr int kPiece = kVecPerTile >= 64 ? kVecPerTile / 64 : 1;
-            const int pieces = nt * kPiece, per = (pieces + W - 1) / W;
+            const int pieces = nt * kPiece, per = (pieces + P - 1) / P;
             const int c0 = min(pieces, wave * per), c1 = min(pieces, c0 + per);
-            const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)smem;
             if (c0 < c1) {
                 int base = c0 / kPiece;
                 i32x4 tl = sload_x4(a.tile_list + q0 + base);
@@ -372,29 +387,44 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     __syncthreads();
 
     for (int s = s0; s < s1; ++s) {
-        int n;
-        if constexpr (kDma) {
-            const i32x4 sb = sload_x4(a.slab + p0 + (s - s0));  // two int64 bounds
-            n = sb.z - sb.x;  // a slab holds far fewer than 2^31 groups
-        } else {
-            n = (int)(a.slab[p0 + (s - s0) + 1] - a.slab[p0 + (s - s0)]);
-        }
-        // consume this stage's n groups, the first one in slot ph; every
-        // consumed slot is refilled from the cursor, possibly with a later
-        // stage's group
-        for (int i = -ph; i < n; i += D) {
-            prio_for_remaining(n - i);
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int k = i + d;
-                if (k >= 0 && k < n) {
-                    use_group<FMT, F>(e[d], cb, acc);
-                    sg[d] = take();
+        // group counts of this stage's RT slabs (a slab holds far fewer
+        // than 2^31 groups)
+        int nh[RT];
+        {
+            const int64_t ps = p0 + (int64_t)(s - s0) * RT;
+            if constexpr (kDma) {
+                const i32x4 sb = sload_x4(a.slab + ps);  // two int64 bounds
+                nh[0] = sb.z - sb.x;
+                if constexpr (RT == 2) {
+                    const i32x4 sb1 = sload_x4(a.slab + ps + 1);
+                    nh[1] = sb1.z - sb1.x;
                 }
-                e[d] = load_group<FMT>(rs, sg[d], lane);
+            } else {
+#pragma unroll
+                for (int h = 0; h < RT; ++h) nh[h] = (int)(a.slab[ps + h + 1] - a.slab[ps + h]);
             }
         }
-        ph = (ph + n) % D;
+#pragma unroll
+        for (int h = 0; h < RT; ++h) {
+            const int n = nh[h];
+            const int later = h + 1 < RT ? nh[RT - 1] : 0;  // groups of the stage after this slab
+            // consume this slab's n groups, the first one in slot ph; every
+            // consumed slot is refilled from the cursor, possibly with a
+            // later slab's group
+            for (int i = -ph; i < n; i += D) {
+                prio_for_remaining(n - i + later);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int k = i + d;
+                    if (k >= 0 && k < n) {
+                        use_group<FMT, F, KB>(e[d], cb, acc[h]);
+                        sg[d] = take();
+                    }
+                    e[d] = load_group<FMT>(rs, sg[d], lane);
+                }
+            }
+            ph = (ph + n) % D;
+        }
         __builtin_amdgcn_s_setprio(0);
 
         if (s + 1 < s1) {
@@ -408,46 +438,55 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
 
     // Undo the chunk rotation: slice c*SPC + t of this lane's row is in
     // accumulator block j = (c - lane) mod CH.
-    float y[F];
+    double sq[F];  // this lane's per-slice sum of squares over its RT rows
 #pragma unroll
-    for (int c = 0; c < R::CH; ++c) {
+    for (int f = 0; f < F; ++f) sq[f] = 0.0;
 #pragma unroll
-        for (int t = 0; t < R::SPC; ++t) {
-            float v = acc[t];
+    for (int h = 0; h < RT; ++h) {
+        float y[F];
 #pragma unroll
-            for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? acc[j * R::SPC + t] : v;
-            y[c * R::SPC + t] = v;
+        for (int c = 0; c < R::CH; ++c) {
+#pragma unroll
+            for (int t = 0; t < R::SPC; ++t) {
+                float v = acc[h][t];
+#pragma unroll
+                for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? acc[h][j * R::SPC + t] : v;
+                y[c * R::SPC + t] = v;
+            }
         }
-    }
-    if (a.scale) {
+        if (a.scale) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) y[f] *= a.scale[f];
-    }
-    const int64_t rt = (int64_t)b * W + wave;
-    if (rt < a.n_row_tiles) {
-        float *out = a.yout + (rt * kTileSlots + lane_slot(lane, a.lanes)) * F;
-        if constexpr (F >= 4) {
-#pragma unroll
-            for (int q = 0; q < F / 4; ++q) ((f32x4 *)out)[q] = f32x4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
-        } else {
-#pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = y[f];
+            for (int f = 0; f < F; ++f) y[f] *= a.scale[f];
         }
+        const int64_t rt = (int64_t)b * W + h * P + wave;
+        if (rt < a.n_row_tiles) {
+            float *out = a.yout + (rt * kTileSlots + lane_slot(lane, a.lanes)) * F;
+            if constexpr (F >= 4) {
+#pragma unroll
+                for (int q = 0; q < F / 4; ++q)
+                    ((f32x4 *)out)[q] = f32x4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+            } else {
+#pragma unroll
+                for (int f = 0; f < F; ++f) out[f] = y[f];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) sq[f] += (double)y[f] * (double)y[f];
     }
     if (a.sq_partial) {
         // per-slice sum of squares of this block's outputs, in FP64, fixed order
         __syncthreads();
-        double *red = (double *)smem;  // [W][F]
+        double *red = (double *)smem;  // [P][F]
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            double q = (double)y[f] * (double)y[f];
+            double q = sq[f];
             for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
             if (lane == 0) red[wave * F + f] = q;
         }
         __syncthreads();
         if (tid < F) {
             double q = 0.0;
-            for (int w = 0; w < W; ++w) q += red[w * F + tid];
+            for (int w = 0; w < P; ++w) q += red[w * F + tid];
             a.sq_partial[(int64_t)b * F + tid] = q;
         }
     }
@@ -461,7 +500,7 @@ struct ProfileRec {
 };
 static ProfileRec g_prof;
 
-template <int FMT, int F>
+template <int FMT, int F, int RT>
 static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     const OpPlan &op = *L.op;
     SpmmArgs a;
@@ -481,13 +520,14 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.T = op.T;
     a.remap = L.remap;
     a.lanes = op.lanes;
+    a.W = op.W;
     typedef typename Stor<FMT>::T XT;
     size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
     const size_t red = sizeof(double) * (size_t)op.W * F;
     if (smem < red) smem = red;
     static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far
     if ((int)smem > attr_bytes) {
-        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F, RT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem));
         attr_bytes = (int)smem;
     }
@@ -499,7 +539,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
         XCT_HIP_TRY(hipEventCreate(&e1));
         XCT_HIP_TRY(hipEventRecord(e0, st));
     }
-    hipLaunchKernelGGL((k_spmm<FMT, F>), dim3(grid), dim3(op.W * kTileSlots), smem, st, a);
+    hipLaunchKernelGGL((k_spmm<FMT, F, RT>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
     XCT_HIP_TRY(hipGetLastError());
     if (g_prof.on) {
         XCT_HIP_TRY(hipEventRecord(e1, st));
@@ -508,15 +548,24 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     return XCT_OK;
 }
 
+template <int FMT, int RT>
+static int launch_rt(const SpmmLaunch &L, hipStream_t st) {
+    switch (L.F) {
+        case 1: return launch_one<FMT, 1, RT>(L, st);
+        case 2: return launch_one<FMT, 2, RT>(L, st);
+        case 4: return launch_one<FMT, 4, RT>(L, st);
+        case 8: return launch_one<FMT, 8, RT>(L, st);
+        case 16: return launch_one<FMT, 16, RT>(L, st);
+        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    }
+}
+
 template <int FMT>
 static int launch_fmt(const SpmmLaunch &L, hipStream_t st) {
-    switch (L.F) {
-        case 1: return launch_one<FMT, 1>(L, st);
-        case 2: return launch_one<FMT, 2>(L, st);
-        case 4: return launch_one<FMT, 4>(L, st);
-        case 8: return launch_one<FMT, 8>(L, st);
-        case 16: return launch_one<FMT, 16>(L, st);
-        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    switch (L.op->R) {
+        case 1: return launch_rt<FMT, 1>(L, st);
+        case 2: return launch_rt<FMT, 2>(L, st);
+        default: return fail(XCT_ERR_INTERNAL, "unsupported row tiles per wavefront");
     }
 }
 

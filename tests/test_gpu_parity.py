@@ -80,6 +80,28 @@ def test_matrix_entries_match_oracle(N, M, C, dt):
         assert info["nnz"] == ref.nnz
 
 
+@pytest.mark.parametrize("dt", ["f32", "f16"])
+@pytest.mark.parametrize("N,M,C", [(128, 180, 128), (37, 23, 41)])
+def test_matrix_entries_two_row_tiles_per_wavefront(N, M, C, dt):
+    # 32 row tiles per block on 16 wavefronts: every entry decodes to the
+    # oracle's (row, column) once, with its rounded length
+    banner(f"entries W=32 N={N} M={M} C={C} {dt}")
+    A = gpu_matrix(N, M, C, dt, tile_waves=32)
+    Ao, ATo = oracle_mats(N, M, C)
+    npdt = {"f32": np.float32, "f16": np.float16}[dt]
+    for which, ref in ((0, Ao.tocoo()), (1, ATo.tocoo())):
+        r, c, v = A.to_coo(which)
+        rv = ref.data.astype(npdt).astype(np.float32)
+        keep = rv != 0
+        rk = ref.row[keep].astype(np.int64) * ref.shape[1] + ref.col[keep]
+        gk = r.astype(np.int64) * ref.shape[1] + c
+        og, oo = np.argsort(gk), np.argsort(rk)
+        np.testing.assert_array_equal(gk[og], rk[oo])
+        gv, ov = v[og], rv[keep][oo]
+        ulp = np.spacing(ov.astype(npdt)).astype(np.float32)
+        assert np.all(np.abs(gv - ov) <= ulp), np.abs(gv - ov).max()
+
+
 @pytest.mark.parametrize("N,M,C", GEOMS)
 @pytest.mark.parametrize("B", [1, 3, 16, 17])
 def test_project_backproject_parity(N, M, C, B):
@@ -102,7 +124,9 @@ def test_project_backproject_parity(N, M, C, B):
 @pytest.mark.parametrize("opts", [dict(stage_order=1), dict(tile_waves=4, lds_bytes=32768),
                                   dict(tile_waves=16, xcd_remap=-1), dict(fuse=4), dict(fuse=2),
                                   dict(lane_order=1), dict(tile_waves=16, lds_bytes=163840),
-                                  dict(slab_order=1), dict(fuse=8), dict(fuse=8, lane_order=1)])
+                                  dict(slab_order=1), dict(fuse=8), dict(fuse=8, lane_order=1),
+                                  dict(tile_waves=32), dict(tile_waves=32, fuse=8), dict(tile_waves=32, fuse=1),
+                                  dict(tile_waves=32, fuse=4, lds_bytes=32768), dict(tile_waves=32, slab_order=1)])
 def test_plan_options_keep_parity(opts):
     N, M, C, B = 64, 90, 64, 5
     A = gpu_matrix(N, M, C, **opts)
@@ -212,6 +236,19 @@ def test_cgls_early_iterations_match_oracle(N, M, C, B, iters):
         e = rel_err(xg.cpu().numpy(), xo)
         banner(f"  k={k} rel err {e.max():.2e}")
         assert e.max() <= 1e-5, e
+        np.testing.assert_allclose(resg, reso, rtol=1e-5, atol=1e-8)
+        assert np.all(stg == sto)
+
+
+def test_cgls_two_row_tiles_per_wavefront():
+    # the per-block sums of squares cover both row tiles of each wavefront
+    N, M, C, B = 64, 90, 64, 5
+    A = gpu_matrix(N, M, C, tile_waves=32)
+    Ao, ATo, _, y = cgls_problem(N, M, C, B)
+    for k in (1, 4):
+        xg, resg, stg = xct.cgls(A, y.cuda(), k)
+        xo, reso, sto = oracle.cgls(Ao, ATo, y.double().numpy().reshape(B, -1), k)
+        assert rel_err(xg.cpu().numpy(), xo).max() <= 1e-5
         np.testing.assert_allclose(resg, reso, rtol=1e-5, atol=1e-8)
         assert np.all(stg == sto)
 
