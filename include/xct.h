@@ -69,7 +69,8 @@ enum {
 
 /* Build options; zero in any field selects the default. */
 typedef struct {
-    int tile_waves; /* row tiles (64 rows each, one wavefront) per workgroup; default 16, max 16 */
+    int tile_waves; /* row tiles (64 rows each) per workgroup: 1..16 (one wavefront each) or 32
+                       (16 wavefronts holding two row tiles each); default 16 */
     int fuse;       /* largest number of slices fused per matrix pass (F); 1,2,4,8 or 16; default 16 */
     int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input
                        (T = lds_bytes / (64 * F * element size) input tiles, at most 1024);
