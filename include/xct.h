@@ -164,6 +164,41 @@ int xct_project(const xct_matrix *A, const void *x, void *y, int batch, xct_dtyp
 int xct_backproject(const xct_matrix *A, const void *y, void *x, int batch, xct_dtype io,
                     void *workspace, void *stream);
 
+/* Device workspace needed by xct_project_streamed (which = 0) or
+ * xct_backproject_streamed (which = 1) for chunks of `chunk` slices of dtype `io`. */
+size_t xct_stream_workspace_bytes(const xct_matrix *A, int which, int chunk, xct_dtype io);
+
+/*
+ * Streamed forward projection y_b = A x_b for b < batch, with x and y in host
+ * memory (slices moved to and from the device in chunks, the single-GPU form
+ * of the minibatch pipelining of Sec. III-A/III-D).  Chunk c's host-to-device
+ * copy runs on h2d_stream, its product (as xct_project, on `chunk` slices)
+ * on compute_stream and its device-to-host copy on d2h_stream, so copies of
+ * one chunk overlap the products of its neighbours (two device buffers per
+ * direction).  Results equal xct_project's on the same slices.
+ *   x_host     host, [batch][n][n] of dtype `io`; page-locked for the copies
+ *              to run asynchronously (else they serialise)
+ *   y_host     host, [batch][n_angles][n_channels] of dtype `io` (written)
+ *   chunk      slices per transfer, >= 1 (a multiple of the matrix's fuse
+ *              keeps every fused group full)
+ *   workspace  device, >= xct_stream_workspace_bytes(A, 0, chunk, io) bytes, 256-B aligned
+ *   streams    HIP streams (NULL: the default stream; equal streams serialise).  The
+ *              workspace belongs to compute_stream's order: the copy streams first
+ *              wait for the work already enqueued there.
+ * Returns after every result is in y_host (the three streams are drained,
+ * also on error).  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ */
+int xct_project_streamed(const xct_matrix *A, const void *x_host, void *y_host, int batch, int chunk,
+                         xct_dtype io, void *workspace, void *compute_stream, void *h2d_stream,
+                         void *d2h_stream);
+
+/* Streamed backprojection x_b = A^T y_b; as xct_project_streamed with the
+ * roles of x and y exchanged (y_host is read, x_host written; which = 1 for
+ * the workspace size). */
+int xct_backproject_streamed(const xct_matrix *A, const void *y_host, void *x_host, int batch, int chunk,
+                             xct_dtype io, void *workspace, void *compute_stream, void *h2d_stream,
+                             void *d2h_stream);
+
 /* Device workspace needed by xct_cgls for `batch` slices and `iters` iterations. */
 size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
 

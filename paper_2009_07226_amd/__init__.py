@@ -4,8 +4,9 @@ hot path of parallel-beam XCT reconstruction (Hidayetoglu et al., SC20).
 The kernels live in libxct.so (C ABI: include/xct.h); this package is its
 thin binding plus seeded input generators.
 """
-from .xct import (BF16, F16, F32, Matrix, XctBackproject, XctError, XctProject, backproject, cgls, lib,
-                  library_loaded, profile_enable, profile_read, project, read_bandwidth)
+from .xct import (BF16, F16, F32, Matrix, XctBackproject, XctError, XctProject, backproject,
+                  backproject_streamed, cgls, lib, library_loaded, profile_enable, profile_read, project,
+                  project_streamed, read_bandwidth)
 
-__all__ = ["Matrix", "project", "backproject", "cgls", "XctProject", "XctBackproject", "XctError", "lib",
+__all__ = ["Matrix", "project", "backproject", "project_streamed", "backproject_streamed", "cgls", "XctProject", "XctBackproject", "XctError", "lib",
            "library_loaded", "profile_enable", "profile_read", "read_bandwidth", "F32", "F16", "BF16"]

@@ -129,6 +129,12 @@ struct SpmmLaunch {
     int remap;
 };
 int launch_spmm(const SpmmLaunch &L, hipStream_t s);
+// One projection (dir 0) or backprojection (dir 1) of `batch` device slices
+// in natural layout, as xct_project / xct_backproject; workspace of
+// spmm_workspace(m, batch) bytes, 256-byte aligned.
+int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io, void *workspace,
+              void *stream);
+size_t spmm_workspace(const xct_matrix *m, int batch);
 
 // Natural <-> internal layout conversion for one fused group.
 //   natural: [batch][H][Wd] of dtype io; group covers slices s0 .. s0+F-1

@@ -828,7 +828,7 @@ static size_t spmm_ws_layout(const xct_matrix *m, int batch, char *base, SpmmWs 
     return in_b + out_b + small;
 }
 
-static int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
+int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
                      void *workspace, void *stream) {
     if (!m || !src || !dst || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
     if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
@@ -860,13 +860,15 @@ static int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, i
     return XCT_OK;
 }
 
+size_t spmm_workspace(const xct_matrix *m, int batch) { return spmm_ws_layout(m, batch, nullptr, nullptr); }
+
 }  // namespace xct
 
 using namespace xct;
 
 extern "C" size_t xct_spmm_workspace_bytes(const xct_matrix *m, int batch) {
     if (!m || batch < 1) return 0;
-    return spmm_ws_layout(m, batch, nullptr, nullptr);
+    return spmm_workspace(m, batch);
 }
 
 extern "C" int xct_project(const xct_matrix *m, const void *x, void *y, int batch, xct_dtype io, void *workspace,

@@ -93,6 +93,12 @@ def lib():
     L.xct_profile_read.restype = i
     L.xct_read_bandwidth.argtypes = [vp, i64, i, ctypes.POINTER(ctypes.c_double), vp]
     L.xct_read_bandwidth.restype = i
+    L.xct_stream_workspace_bytes.argtypes = [vp, i, i, i]
+    L.xct_stream_workspace_bytes.restype = sz
+    L.xct_project_streamed.argtypes = [vp, vp, vp, i, i, i, vp, vp, vp, vp]
+    L.xct_project_streamed.restype = i
+    L.xct_backproject_streamed.argtypes = [vp, vp, vp, i, i, i, vp, vp, vp, vp]
+    L.xct_backproject_streamed.restype = i
     L.xct_last_error.argtypes = []
     L.xct_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -233,6 +239,64 @@ def backproject(A: Matrix, y: torch.Tensor, out: Optional[torch.Tensor] = None,
     _check(lib().xct_backproject(A.handle, y.data_ptr(), out.data_ptr(), B, _dt(y.dtype), workspace.data_ptr(),
                                  _stream()))
     return out
+
+
+def _require_host(t: torch.Tensor, shape, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cpu":
+        raise ValueError(f"{name} must be in host memory")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dtype not in _TORCH_DT:
+        raise TypeError(f"{name}: unsupported dtype {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+_COPY_STREAMS = {}
+
+
+def _copy_streams(device):
+    # two copy streams per device (host-to-device, device-to-host), default priority
+    if device not in _COPY_STREAMS:
+        _COPY_STREAMS[device] = (torch.cuda.Stream(device=device), torch.cuda.Stream(device=device))
+    return _COPY_STREAMS[device]
+
+
+def _streamed(which: int, A: Matrix, src: torch.Tensor, out: Optional[torch.Tensor], chunk: Optional[int],
+              workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    in_shape, out_shape = (A.vol_shape, A.sino_shape) if which == 0 else (A.sino_shape, A.vol_shape)
+    B = src.shape[0] if src.dim() == 3 else -1
+    _require_host(src, (B,) + in_shape, "input")
+    if out is None:
+        out = torch.empty((B,) + out_shape, dtype=src.dtype, pin_memory=True)
+    _require_host(out, (B,) + out_shape, "out", src.dtype)
+    chunk = int(chunk) if chunk else 16
+    if workspace is None:
+        nb = lib().xct_stream_workspace_bytes(A.handle, which, chunk, _dt(src.dtype))
+        workspace = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    h2d, d2h = _copy_streams(A.device)
+    fn = lib().xct_project_streamed if which == 0 else lib().xct_backproject_streamed
+    _check(fn(A.handle, src.data_ptr(), out.data_ptr(), B, chunk, _dt(src.dtype), workspace.data_ptr(),
+              _stream(), _stream(h2d), _stream(d2h)))
+    return out
+
+
+def project_streamed(A: Matrix, x: torch.Tensor, out: Optional[torch.Tensor] = None, chunk: Optional[int] = None,
+                     workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x for a host batch x of shape (B, n, n) (page-locked for overlap), moved to
+    the GPU `chunk` slices at a time; returns a host (B, n_angles, n_channels) tensor."""
+    return _streamed(0, A, x, out, chunk, workspace)
+
+
+def backproject_streamed(A: Matrix, y: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         chunk: Optional[int] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A^T y for a host batch y of shape (B, n_angles, n_channels), streamed as
+    project_streamed; returns a host (B, n, n) tensor."""
+    return _streamed(1, A, y, out, chunk, workspace)
 
 
 def cgls(A: Matrix, y: torch.Tensor, iters: int, out: Optional[torch.Tensor] = None,

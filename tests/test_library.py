@@ -42,6 +42,9 @@ def test_argument_errors_without_device():
     assert L.xct_project(None, None, None, 1, 0, None, None) == -1
     assert L.xct_cgls(None, None, 0, None, 1, 1, None, None, None, None) == -1
     assert L.xct_spmm_workspace_bytes(None, 4) == 0
+    assert L.xct_stream_workspace_bytes(None, 0, 4, 0) == 0
+    assert L.xct_project_streamed(None, None, None, 1, 1, 0, None, None, None, None) == -1
+    assert L.xct_backproject_streamed(None, None, None, 1, 1, 0, None, None, None, None) == -1
     assert L.xct_cgls_workspace_bytes(None, 4, 3) == 0
     g = ctypes.c_double()
     assert L.xct_read_bandwidth(None, 1 << 20, 1, ctypes.byref(g), None) == -1
