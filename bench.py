@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--tile-waves", type=int, default=0)
     ap.add_argument("--lane-order", type=int, default=0)
     ap.add_argument("--slab-order", type=int, default=0)
+    ap.add_argument("--fuse", type=int, default=0, help="slices fused per matrix pass (1, 2, 4, 8, 16; default 16)")
     ap.add_argument("--streamed", type=int, default=0, metavar="BATCH",
                     help="also time a step over BATCH host-resident slices (streamed entry points, chunks of "
                          "fuse slices, PCIe-inclusive)")
@@ -141,7 +142,7 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     log(f"building {args.dtype} matrix N={N} M={M} C={C}")
-    opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves,
+    opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves, fuse=args.fuse,
                 lane_order=args.lane_order, slab_order=args.slab_order)
     A = xct.Matrix(N, M, C, args.dtype, **opts)
     b_a = 6 if args.dtype == "f32" else 4
@@ -149,7 +150,7 @@ def main():
     info = A.info()
     log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
         f"A^T padded {info['AT']['padded']:,}")
-    F = min(16, 1 << max(0, (B - 1).bit_length()))
+    F = min(int(info["fuse"]), 1 << max(0, (B - 1).bit_length()))  # slices per matrix pass
     nnz = info["A"]["nnz"]
     bytes_A = alg_bytes(nnz, N * N, M * C, B, F, b_a)
     bytes_AT = alg_bytes(info["AT"]["nnz"], M * C, N * N, B, F, b_a)
@@ -248,7 +249,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.dtype, N, M, B,
-                                        not (args.stage_order or args.lds_bytes or args.tile_waves or
+                                        not (args.stage_order or args.lds_bytes or args.tile_waves or args.fuse or
                                              args.lane_order or args.slab_order)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": round(avg_ms, 4),
