@@ -308,9 +308,16 @@ def main():
                 best = min(best, s0.elapsed_time(s1) * 1e-3)
             return best
 
+        def cgls_history(Am):
+            # untimed run with the per-iteration residual history ||y - A x_k|| / ||y||
+            xo, res, _ = xct.cgls(Am, yc, it)
+            return xo, res
+
+        checkpoints = [k for k in (0, 1, 2, 3, 5, 10, 20, 30, 50) if k <= it]
         log("CGLS FP32")
         A32 = A if args.dtype == "f32" else xct.Matrix(N, M, C, "f32", **opts)
         t32 = (cgls_time(A32, it) - cgls_time(A32, 0)) / it
+        x32, res32 = cgls_history(A32)
         del A32
         if args.dtype == "f32":
             del A
@@ -319,6 +326,9 @@ def main():
         A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts)
         log("CGLS FP16 storage")
         t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
+        x16, res16 = cgls_history(A16)
+        d16 = ((x16 - x32).flatten(1).norm(dim=1) / x32.flatten(1).norm(dim=1).clamp_min(1e-30)).max().item()
+        del x32, x16
         # the FP16 operators' projection + backprojection step, for reference
         i16 = A16.info()
         ws16 = A16.spmm_workspace(B)
@@ -344,8 +354,14 @@ def main():
                             "launch_ms": {"A": round(p16["A"][1] / max(p16["A"][0], 1), 4),
                                           "AT": round(p16["AT"][1] / max(p16["AT"][0], 1), 4)},
                             "padded_A": i16["A"]["padded"], "padded_AT": i16["AT"]["padded"]}
+        # convergence against time: median relative residual over the slices
+        # after k iterations, reached at k * s/iter
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),
                        "fp16_speedup": round(t32 / t16, 3),
+                       "residual_median": {"k": checkpoints,
+                                           "fp32": [float(np.median(res32[k])) for k in checkpoints],
+                                           "fp16": [float(np.median(res16[k])) for k in checkpoints]},
+                       "fp16_vs_fp32_rel_l2_max": round(d16, 6),
                        "build_s_f16": round(A16.info()["build_seconds"], 3)}
         log(f"CGLS s/iter FP32 {t32 * 1e3:.3f} ms, FP16 {t16 * 1e3:.3f} ms")
         del A16
