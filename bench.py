@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--lane-order", type=int, default=0)
     ap.add_argument("--slab-order", type=int, default=0)
     ap.add_argument("--fuse", type=int, default=0, help="slices fused per matrix pass (1, 2, 4, 8, 16; default 16)")
+    ap.add_argument("--arith", type=int, default=0,
+                    help="1: FP16 arithmetic for the FP16 matrices (the paper's half-precision variant)")
     ap.add_argument("--streamed", type=int, default=0, metavar="BATCH",
                     help="also time a step over BATCH host-resident slices (streamed entry points, chunks of "
                          "fuse slices, PCIe-inclusive)")
@@ -144,7 +146,8 @@ def main():
     log(f"building {args.dtype} matrix N={N} M={M} C={C}")
     opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves, fuse=args.fuse,
                 lane_order=args.lane_order, slab_order=args.slab_order)
-    A = xct.Matrix(N, M, C, args.dtype, **opts)
+    opts16 = dict(opts, arith=args.arith)  # FP16 arithmetic applies to FP16 matrices only
+    A = xct.Matrix(N, M, C, args.dtype, **(opts16 if args.dtype == "f16" else opts))
     b_a = 6 if args.dtype == "f32" else 4
     b_x = 4 if args.dtype == "f32" else 2
     info = A.info()
@@ -250,6 +253,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.dtype, N, M, B,
                                         not (args.stage_order or args.lds_bytes or args.tile_waves or args.fuse or
+                                             args.arith or
                                              args.lane_order or args.slab_order)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": round(avg_ms, 4),
@@ -323,7 +327,7 @@ def main():
             del A
         torch.cuda.empty_cache()
         log("building FP16 matrix")
-        A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts)
+        A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts16)
         log("CGLS FP16 storage")
         t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
         x16, res16 = cgls_history(A16)

@@ -87,6 +87,10 @@ typedef struct {
                         0 (default) scheduled so that the lanes served together by one
                           16-byte LDS read hit distinct bank groups (rows of 32 or 64 B);
                         1 ray/voxel tracing order */
+    int arith;       /* arithmetic of the products: 0 (default) FP32 accumulation; 1 FP16
+                        accumulation with packed FP16 FMAs (FP16 matrices only; the paper's
+                        "half precision" variant, for measurement: sums keep ~11 bits, so
+                        results deviate by ~1e-2 relative; a single fused slice keeps FP32) */
 } xct_build_opts;
 
 /* Statistics of one operator (A or A^T). */

@@ -1048,6 +1048,9 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
     if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
     if (o.slab_order < 0 || o.slab_order > 1) return fail(XCT_ERR_INVALID, "slab_order must be 0 or 1");
+    if (o.arith < 0 || o.arith > 1) return fail(XCT_ERR_INVALID, "arith must be 0 or 1");
+    if (o.arith == 1 && value_dtype != XCT_F16)
+        return fail(XCT_ERR_UNSUPPORTED, "FP16 arithmetic needs an FP16 matrix");
     const int row_bytes = F * elem_bytes(value_dtype);
     const int lanes = o.lane_order;
     auto t0 = std::chrono::steady_clock::now();
@@ -1088,6 +1091,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
             rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, row_bytes,
                           o.slab_order == 0, st);
     }
+    m->A.arith16 = m->AT.arith16 = o.arith == 1 ? 1 : 0;
     if (rc) {
         std::string msg = g_last_error;
         xct_free_matrix(m);

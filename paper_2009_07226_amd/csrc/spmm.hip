@@ -213,6 +213,48 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&
     }
 }
 
+// FP16 arithmetic (the paper's "half precision" variant, measurement only):
+// F/2 packed FP16 accumulators, one v_pk_fma_f16 per two slices and entry.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+template <int F, int KB>
+__device__ __forceinline__ void use_group_h16(const Group<XCT_F16> &g,
+                                              const uint32_t (&cb)[RowShape<XCT_F16, F>::CH], h2 (&acc)[F / 2]) {
+    typedef RowShape<XCT_F16, F> R;
+    static_assert(R::SPC % 2 == 0, "pairs of slices per chunk");
+    const uint32_t p[4] = {g.p.x, g.p.y, g.p.z, g.p.w};
+#pragma unroll
+    for (int q0 = 0; q0 < kGroup; q0 += KB) {
+        u32x4 w[KB][R::CH];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+#pragma unroll
+            for (int j = 0; j < R::CH; ++j) {
+                const uint32_t ad = row_addr<R::RB, true>(p[q0 + k], cb[j]);
+                if constexpr (R::RB >= 16)
+                    w[k][j] = *lds_ptr<u32x4>(ad);
+                else
+                    w[k][j] = load_small<R::RB>(ad);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the FMAs
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const _Float16 vh = __builtin_bit_cast(_Float16, (uint16_t)(p[q0 + k] & 0xffffu));
+            const h2 v2 = {vh, vh};
+#pragma unroll
+            for (int j = 0; j < R::CH; ++j) {
+                const uint32_t u[4] = {w[k][j].x, w[k][j].y, w[k][j].z, w[k][j].w};
+#pragma unroll
+                for (int t = 0; t < R::SPC / 2; ++t) {
+                    const h2 x2 = __builtin_bit_cast(h2, u[t]);
+                    acc[j * (R::SPC / 2) + t] = __builtin_elementwise_fma(v2, x2, acc[j * (R::SPC / 2) + t]);
+                }
+            }
+        }
+    }
+}
+
 // Scalar loads of wave-uniform metadata (p wave-uniform).  Once the stage
 // loop holds the global-to-LDS copy (which the compiler treats as a write to
 // memory), it no longer proves these read-only arrays unwritten and turns
@@ -253,8 +295,9 @@ template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
 template <int FMT, int F, int RT> struct ReadBatch { static constexpr int value = 4; };
 template <> struct ReadBatch<XCT_F32, 16, 2> { static constexpr int value = 2; };
 
-// RT: row tiles per wavefront (a.W / RT wavefronts per block).
-template <int FMT, int F, int RT>
+// RT: row tiles per wavefront (a.W / RT wavefronts per block); H16: FP16
+// arithmetic on an FP16 matrix (F >= 2).
+template <int FMT, int F, int RT, bool H16>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spmm(SpmmArgs a) {
     typedef RowShape<FMT, F> R;
     constexpr int D = RingDepth<FMT>::value;
@@ -280,11 +323,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         coff[j] = ((j + lane) & (R::CH - 1)) * 16;
         cb[j] = lds_addr(smem) + coff[j];
     }
-    float acc[RT][F];
+    static_assert(!H16 || (FMT == XCT_F16 && F >= 2), "FP16 arithmetic needs an FP16 matrix and F >= 2");
+    float acc[RT][H16 ? 1 : F];
+    h2 acc2[RT][H16 ? F / 2 : 1];
 #pragma unroll
-    for (int h = 0; h < RT; ++h)
+    for (int h = 0; h < RT; ++h) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[h][f] = 0.f;
+        for (int f = 0; f < (H16 ? 1 : F); ++f) acc[h][f] = 0.f;
+#pragma unroll
+        for (int f = 0; f < (H16 ? F / 2 : 1); ++f) acc2[h][f] = h2{(_Float16)0, (_Float16)0};
+    }
 
     constexpr int kVecPerTile = kTileSlots * R::RB / 16;  // 16-byte vectors per staged tile
     // stages of rows of 16 bytes or more are copied straight into LDS
@@ -417,7 +465,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
                 for (int d = 0; d < D; ++d) {
                     const int k = i + d;
                     if (k >= 0 && k < n) {
-                        use_group<FMT, F, KB>(e[d], cb, acc[h]);
+                        if constexpr (H16)
+                            use_group_h16<F, KB>(e[d], cb, acc2[h]);
+                        else
+                            use_group<FMT, F, KB>(e[d], cb, acc[h]);
                         sg[d] = take();
                     }
                     e[d] = load_group<FMT>(rs, sg[d], lane);
@@ -443,14 +494,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     for (int f = 0; f < F; ++f) sq[f] = 0.0;
 #pragma unroll
     for (int h = 0; h < RT; ++h) {
+        float af[F];  // the row's sums in accumulator order, FP32
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if constexpr (H16)
+                af[f] = (float)((f & 1) ? acc2[h][f >> 1].y : acc2[h][f >> 1].x);
+            else
+                af[f] = acc[h][f];
+        }
         float y[F];
 #pragma unroll
         for (int c = 0; c < R::CH; ++c) {
 #pragma unroll
             for (int t = 0; t < R::SPC; ++t) {
-                float v = acc[h][t];
+                float v = af[t];
 #pragma unroll
-                for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? acc[h][j * R::SPC + t] : v;
+                for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? af[j * R::SPC + t] : v;
                 y[c * R::SPC + t] = v;
             }
         }
@@ -500,7 +559,7 @@ struct ProfileRec {
 };
 static ProfileRec g_prof;
 
-template <int FMT, int F, int RT>
+template <int FMT, int F, int RT, bool H16>
 static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     const OpPlan &op = *L.op;
     SpmmArgs a;
@@ -527,7 +586,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     if (smem < red) smem = red;
     static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far
     if ((int)smem > attr_bytes) {
-        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F, RT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F, RT, H16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem));
         attr_bytes = (int)smem;
     }
@@ -539,7 +598,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
         XCT_HIP_TRY(hipEventCreate(&e1));
         XCT_HIP_TRY(hipEventRecord(e0, st));
     }
-    hipLaunchKernelGGL((k_spmm<FMT, F, RT>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
+    hipLaunchKernelGGL((k_spmm<FMT, F, RT, H16>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
     XCT_HIP_TRY(hipGetLastError());
     if (g_prof.on) {
         XCT_HIP_TRY(hipEventRecord(e1, st));
@@ -548,14 +607,24 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     return XCT_OK;
 }
 
+// FP16 arithmetic where the operator asks for it (FP16 matrices, F >= 2;
+// a single fused slice keeps FP32 arithmetic).
+template <int FMT, int F, int RT>
+static int launch_arith(const SpmmLaunch &L, hipStream_t st) {
+    if constexpr (FMT == XCT_F16 && F >= 2) {
+        if (L.op->arith16) return launch_one<FMT, F, RT, true>(L, st);
+    }
+    return launch_one<FMT, F, RT, false>(L, st);
+}
+
 template <int FMT, int RT>
 static int launch_rt(const SpmmLaunch &L, hipStream_t st) {
     switch (L.F) {
-        case 1: return launch_one<FMT, 1, RT>(L, st);
-        case 2: return launch_one<FMT, 2, RT>(L, st);
-        case 4: return launch_one<FMT, 4, RT>(L, st);
-        case 8: return launch_one<FMT, 8, RT>(L, st);
-        case 16: return launch_one<FMT, 16, RT>(L, st);
+        case 1: return launch_arith<FMT, 1, RT>(L, st);
+        case 2: return launch_arith<FMT, 2, RT>(L, st);
+        case 4: return launch_arith<FMT, 4, RT>(L, st);
+        case 8: return launch_arith<FMT, 8, RT>(L, st);
+        case 16: return launch_arith<FMT, 16, RT>(L, st);
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
 }

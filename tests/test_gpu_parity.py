@@ -376,3 +376,43 @@ def test_sampled_rows_at_size_512():
     ref = oracle.backproject_voxels(N, M, C, ys.double().numpy(), vox)
     got = xb.reshape(B, -1)[:, vox].double().numpy()
     assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("B", [5, 16])
+def test_fp16_arithmetic_within_rounding_bound(B):
+    # The paper's "half precision" variant: FP16 storage and FP16 sums.  Each
+    # of a row's k additions rounds to 11 bits; with round-to-nearest the
+    # errors behave like a random walk, so the relative error of a sum stays
+    # within a few sqrt(k) * 2^-11 (here 4x, plus the operand's own rounding).
+    N, M, C = 128, 180, 128
+    Ao, ATo = oracle_mats(N, M, C)
+    A16 = gpu_matrix(N, M, C, "f16")
+    A16h = gpu_matrix(N, M, C, "f16", arith=1)
+    x = phantoms.ellipse_batch(N, B, 6, seed=31).float()
+    xr = oracle.project(Ao, x.double().numpy().reshape(B, -1))
+    u = 2.0 ** -11
+    bound_A = 4 * np.sqrt(Ao.getnnz(axis=1).max()) * u + 2 * u
+    y16 = xct.project(A16, x.cuda()).cpu()
+    y16h = xct.project(A16h, x.cuda()).cpu()
+    e = rel_err(y16h.numpy(), xr)
+    banner(f"FP16 arithmetic A x: max rel err {e.max():.2e} (bound {bound_A:.2e}); FP32 sums "
+           f"{rel_err(y16.numpy(), xr).max():.2e}")
+    assert e.max() <= bound_A
+    assert not torch.equal(y16h, y16)  # the FP16-sum kernel ran
+    yr = torch.from_numpy(xr).float().reshape(B, M, C)
+    xb = xct.backproject(A16h, yr.cuda()).cpu()
+    bound_AT = 4 * np.sqrt(ATo.getnnz(axis=1).max()) * u + 2 * u
+    e = rel_err(xb.numpy(), oracle.backproject(ATo, yr.double().numpy()))
+    assert e.max() <= bound_AT
+
+
+def test_fp16_arithmetic_options():
+    with pytest.raises(xct.XctError):
+        gpu_matrix(16, 12, 16, "f32", arith=1)
+    with pytest.raises(xct.XctError):
+        gpu_matrix(16, 12, 16, "bf16", arith=1)
+    # a single fused slice keeps FP32 sums
+    A16 = gpu_matrix(37, 23, 41, "f16")
+    A16h = gpu_matrix(37, 23, 41, "f16", arith=1)
+    x = phantoms.ellipse_batch(37, 1, 4, seed=5).float().cuda()
+    assert torch.equal(xct.project(A16, x), xct.project(A16h, x))
