@@ -285,10 +285,14 @@ __device__ __forceinline__ void prio_for_remaining(int rem) {
         __builtin_amdgcn_s_setprio(0);
 }
 
-// Entries in flight per wavefront: the ring holds the next kRing groups of
-// the wave's entry stream, which runs through all stages of the block.
-template <int FMT> struct RingDepth { static constexpr int value = 6; };
-template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
+// Entries in flight per wavefront: the ring holds the next D groups of the
+// wave's entry stream, which runs through all stages of the block.  Every
+// pass reloads all D slots, so a stage whose group count is not a multiple
+// of D re-reads some groups; with four wavefronts per SIMD hiding the
+// latency, shallow rings measured fastest (FP32: D = 2 beat 3, 4, 5, 6 by
+// 3-9%; FP16: D = 3 or 4 beat 2, 6, 8).
+template <int FMT> struct RingDepth { static constexpr int value = 4; };
+template <> struct RingDepth<XCT_F32> { static constexpr int value = 2; };
 
 // LDS reads issued together: the whole group, or half of it when a
 // wavefront holds two FP32 accumulator sets of 16 slices (register budget).
