@@ -286,13 +286,13 @@ __device__ __forceinline__ void prio_for_remaining(int rem) {
 }
 
 // Entries in flight per wavefront: the ring holds the next D groups of the
-// wave's entry stream, which runs through all stages of the block.  Every
-// pass reloads all D slots, so a stage whose group count is not a multiple
-// of D re-reads some groups; with four wavefronts per SIMD hiding the
-// latency, shallow rings measured fastest (FP32: D = 2 beat 3, 4, 5, 6 by
-// 3-9%; FP16: D = 3 or 4 beat 2, 6, 8).
+// wave's entry stream, which runs through all stages of the block.  In the
+// stage-by-stage loop (16-bit matrices) every pass reloads all D slots, so a
+// stage whose group count is not a multiple of D re-reads some groups: D = 3
+// or 4 measured fastest (2, 6 and 8 slower).  The flat loop (FP32) reloads a
+// slot only once consumed: D = 4 measured best there (2: +2%, 3: +0.3%).
 template <int FMT> struct RingDepth { static constexpr int value = 4; };
-template <> struct RingDepth<XCT_F32> { static constexpr int value = 2; };
+template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
 
 // LDS reads issued together: the whole group, or half of it when a
 // wavefront holds two FP32 accumulator sets of 16 slices (register budget).
@@ -372,6 +372,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         ++lg;
         return g;
     };
+    constexpr bool kFlat = FMT == XCT_F32;
     Group<FMT> e[D];
     int sg[D];
 #pragma unroll
@@ -379,7 +380,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         sg[d] = take();
         e[d] = load_group<FMT>(rs, sg[d], lane);
     }
-    int ph = 0;  // ring slot holding the next group
 
     // Copy of one stage into LDS.  Vector c (16 bytes) of a stage that starts
     // at tile-list position q0 comes from tile tile_list[q0 + c / kVecPerTile]
@@ -437,13 +437,21 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
 
     if (s0 < s1) copy_static(t0, min(a.T, t1 - t0));
     __syncthreads();
+    int ph = 0;  // ring slot holding the next group (stage-by-stage loop)
 
-    for (int s = s0; s < s1; ++s) {
-        // group counts of this stage's RT slabs (a slab holds far fewer
-        // than 2^31 groups)
-        int nh[RT];
-        {
-            const int64_t ps = p0 + (int64_t)(s - s0) * RT;
+    // FP32 matrices consume the stream in one flat loop; 16-bit matrices,
+    // whose groups carry fewer FMAs, stage by stage (measured: the flat
+    // loop is 3% faster at FP32 and 4% slower at FP16).
+    if constexpr (kFlat) {
+        // The wave's stream is a sequence of slab segments (stage s, row tile
+        // h) consumed in one flat loop: the ring's slots are used in turn and
+        // each is reloaded only after being consumed, rounds running across
+        // segment and stage boundaries (so no group is fetched twice); the
+        // stage transition (barrier, copy, barrier) happens where the stream
+        // crosses into the next stage.  Every wave makes every transition.
+        int nh[RT];  // group counts of stage s's RT slabs (far fewer than 2^31)
+        auto stage_counts = [&](int st) {
+            const int64_t ps = p0 + (int64_t)(st - s0) * RT;
             if constexpr (kDma) {
                 const i32x4 sb = sload_x4(a.slab + ps);  // two int64 bounds
                 nh[0] = sb.z - sb.x;
@@ -453,41 +461,113 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
                 }
             } else {
 #pragma unroll
-                for (int h = 0; h < RT; ++h) nh[h] = (int)(a.slab[ps + h + 1] - a.slab[ps + h]);
+                for (int hh = 0; hh < RT; ++hh) nh[hh] = (int)(a.slab[ps + hh + 1] - a.slab[ps + hh]);
             }
-        }
-#pragma unroll
-        for (int h = 0; h < RT; ++h) {
-            const int n = nh[h];
-            const int later = h + 1 < RT ? nh[RT - 1] : 0;  // groups of the stage after this slab
-            // consume this slab's n groups, the first one in slot ph; every
-            // consumed slot is refilled from the cursor, possibly with a
-            // later slab's group
-            for (int i = -ph; i < n; i += D) {
-                prio_for_remaining(n - i + later);
+        };
+        int st = s0, h = 0, left = 0;
+        // Move to the next segment with groups left, crossing stage boundaries;
+        // false once the stream and every remaining transition are done.
+        auto advance = [&]() -> bool {
+            while (left == 0) {
+                if (h + 1 < RT) {
+                    ++h;
+                    left = nh[h];
+                    continue;
+                }
+                __builtin_amdgcn_s_setprio(0);
+                if (st + 1 >= s1) return false;
+                const int q0n = t0 + (st + 1 - s0) * a.T;
+                const int ntn = min(a.T, t1 - q0n);
+                __syncthreads();  // every wave is done with this stage's data
+                copy_static(q0n, ntn);
+                __syncthreads();  // next stage in place
+                ++st;
+                stage_counts(st);
+                h = 0;
+                left = nh[0];
+            }
+            return true;
+        };
+        if (s0 < s1) {
+            stage_counts(st);
+            left = nh[0];
+            bool more = advance();
+            while (more) {
+                prio_for_remaining(left + (h + 1 < RT ? nh[RT - 1] : 0));
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const int k = i + d;
-                    if (k >= 0 && k < n) {
-                        if constexpr (H16)
-                            use_group_h16<F, KB>(e[d], cb, acc2[h]);
-                        else
-                            use_group<FMT, F, KB>(e[d], cb, acc[h]);
+                    if (more) {
+                        if (RT == 1 || h == 0) {
+                            if constexpr (H16)
+                                use_group_h16<F, KB>(e[d], cb, acc2[0]);
+                            else
+                                use_group<FMT, F, KB>(e[d], cb, acc[0]);
+                        } else {
+                            if constexpr (H16)
+                                use_group_h16<F, KB>(e[d], cb, acc2[RT - 1]);
+                            else
+                                use_group<FMT, F, KB>(e[d], cb, acc[RT - 1]);
+                        }
                         sg[d] = take();
+                        e[d] = load_group<FMT>(rs, sg[d], lane);
+                        --left;
+                        more = advance();
                     }
-                    e[d] = load_group<FMT>(rs, sg[d], lane);
                 }
             }
-            ph = (ph + n) % D;
         }
-        __builtin_amdgcn_s_setprio(0);
+    } else {
+        for (int s = s0; s < s1; ++s) {
+            // group counts of this stage's RT slabs (a slab holds far fewer
+            // than 2^31 groups)
+            int nh[RT];
+            {
+                const int64_t ps = p0 + (int64_t)(s - s0) * RT;
+                if constexpr (kDma) {
+                    const i32x4 sb = sload_x4(a.slab + ps);  // two int64 bounds
+                    nh[0] = sb.z - sb.x;
+                    if constexpr (RT == 2) {
+                        const i32x4 sb1 = sload_x4(a.slab + ps + 1);
+                        nh[1] = sb1.z - sb1.x;
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < RT; ++h) nh[h] = (int)(a.slab[ps + h + 1] - a.slab[ps + h]);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < RT; ++h) {
+                const int n = nh[h];
+                const int later = h + 1 < RT ? nh[RT - 1] : 0;  // groups of the stage after this slab
+                // consume this slab's n groups, the first one in slot ph; every
+                // consumed slot is refilled from the cursor, possibly with a
+                // later slab's group
+                for (int i = -ph; i < n; i += D) {
+                    prio_for_remaining(n - i + later);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        const int k = i + d;
+                        if (k >= 0 && k < n) {
+                            if constexpr (H16)
+                                use_group_h16<F, KB>(e[d], cb, acc2[h]);
+                            else
+                                use_group<FMT, F, KB>(e[d], cb, acc[h]);
+                            sg[d] = take();
+                        }
+                        e[d] = load_group<FMT>(rs, sg[d], lane);
+                    }
+                }
+                ph = (ph + n) % D;
+            }
+            __builtin_amdgcn_s_setprio(0);
 
-        if (s + 1 < s1) {
-            const int q0n = t0 + (s + 1 - s0) * a.T;
-            const int ntn = min(a.T, t1 - q0n);
-            __syncthreads();  // every wave is done with this stage's data
-            copy_static(q0n, ntn);
-            __syncthreads();  // next stage in place
+            if (s + 1 < s1) {
+                const int q0n = t0 + (s + 1 - s0) * a.T;
+                const int ntn = min(a.T, t1 - q0n);
+                __syncthreads();  // every wave is done with this stage's data
+                copy_static(q0n, ntn);
+                __syncthreads();  // next stage in place
+            }
         }
     }
 
