@@ -32,11 +32,37 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/spmm.hip", "csrc/build.hip", "csrc/common.hpp")
 
 
-def kernel_sources_sha() -> str:
+def code_only(text: str) -> str:
+    """C/C++ source with comments removed and whitespace collapsed (string and
+    character literals kept), so that comment edits do not invalidate counters."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == "/" and text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif c == "/" and text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_sources_sha(root: str = HERE) -> str:
+    """SHA-256 of the code (not the comments) of the kernel sources."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root, rel), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 
@@ -82,7 +108,7 @@ def trace_table(stats_csv, out_md, command, workload, note=""):
                      f"{float(r['Percentage']):.2f} | {int(float(r['MinNs']))} | {int(float(r['MaxNs']))} |")
     if note:
         lines += ["", note]
-    lines += ["", f"Kernel sources SHA-256: `{kernel_sources_sha()}`"]
+    lines += ["", f"Kernel sources SHA-256 (code without comments): `{kernel_sources_sha()}`"]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -117,7 +143,7 @@ def main():
         lines.append(f"| {name.split('(')[0]} | {k['launches']} | {k['fetch_bytes_per_launch'] / 1e9:.3f} | "
                      f"{k['write_bytes_per_launch'] / 1e9:.3f} | {', '.join(f'{v:.6g}' for v in k['fetch_kib_raw'])} | "
                      f"{', '.join(f'{v:.6g}' for v in k['write_kib_raw'])} |")
-    lines += ["", f"Kernel sources SHA-256: `{s['kernel_sources_sha256']}`"]
+    lines += ["", f"Kernel sources SHA-256 (code without comments): `{s['kernel_sources_sha256']}`"]
     with open(a.out_prefix + ".md", "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
