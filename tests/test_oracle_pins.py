@@ -311,3 +311,80 @@ def test_cgls_iterates_amplify_rounding():
     x10, _, _ = oracle.cgls(A, AT, y, 10)
     assert envelope(A, AT, y, x4, 4, 1e-7).max() < 1e-5
     assert envelope(A, AT, y, x10, 10, 1e-7).max() > 1e-3
+
+
+# --- The generic gradient solver of Eq. (1) (oracle/gradient.py) ---
+
+def test_tv_gradient_matches_finite_differences():
+    """The hand-derived TV gradient against central differences of TV itself:
+    catches a wrong sign, a shifted index or a dropped boundary term."""
+    from oracle import gradient
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((2, 5, 7))
+    eps, h = 0.3, 1e-6
+    g = gradient.tv_grad(x, eps)
+    fd = np.empty_like(x)
+    for idx in np.ndindex(*x.shape):
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        b = idx[0]
+        fd[idx] = (gradient.tv(xp, eps)[b] - gradient.tv(xm, eps)[b]) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+    # A constant image has zero variation beyond eps per pixel and zero gradient.
+    c = np.full((1, 4, 4), 2.5)
+    assert gradient.tv(c, eps)[0] == pytest.approx(16 * eps)
+    assert np.abs(gradient.tv_grad(c, eps)).max() == 0.0
+
+
+def _nn_problem(N=6, M=8, C=6, seed=3):
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    rng = np.random.default_rng(seed)
+    # A sinogram with negative parts, so the constraint is active somewhere.
+    y = rng.standard_normal((2, M * C)) + 0.5
+    L = 2.0 * np.linalg.norm(A.toarray(), 2) ** 2   # Lipschitz constant of the data gradient
+    return A, AT, y, L
+
+
+def test_projected_gradient_reaches_nnls():
+    """lam = 0, C = {x >= 0}: the fixed point is the NNLS solution, computed
+    independently by scipy's active-set solver (Lawson-Hanson)."""
+    from scipy.optimize import nnls
+    from oracle import gradient
+    A, AT, y, L = _nn_problem()
+    x = gradient.projected_gradient(A, AT, y, 6000, 1.0 / L, lam=0.0)
+    Ad = A.toarray()
+    for b in range(y.shape[0]):
+        ref, _ = nnls(Ad, y[b], maxiter=10000)
+        assert (ref == 0).any(), "constraint inactive: the case would not test the projection"
+        np.testing.assert_allclose(x[b].ravel(), ref, atol=1e-6)
+    # Without the constraint the iteration is Landweber, whose k-th iterate has
+    # a closed form in the SVD basis A = U S V^T: the coefficient along v_i is
+    # (1 - (1 - 2 tau s_i^2)^k) (u_i . y) / s_i.
+    k, tau = 40, 1.0 / L
+    xu = gradient.projected_gradient(A, AT, y, k, tau, lam=0.0, nonneg=False)
+    U, S, Vt = np.linalg.svd(Ad, full_matrices=False)
+    coef = (1.0 - (1.0 - 2.0 * tau * S ** 2) ** k) / S
+    ref = ((U.T @ y.T) * coef[:, None]).T @ Vt
+    np.testing.assert_allclose(xu.reshape(2, -1), ref, rtol=1e-10, atol=1e-12)
+
+
+def test_projected_gradient_with_tv_reaches_bounded_minimiser():
+    """lam > 0: the fixed point minimises Eq. (1) over x >= 0; L-BFGS-B with
+    bounds, on the cost evaluated from its definition with its own
+    finite-difference gradient, finds the same point."""
+    from scipy.optimize import minimize
+    from oracle import gradient
+    A, AT, y, L = _nn_problem(N=5, M=6, C=5, seed=4)
+    lam, eps = 0.7, 0.5
+    step = 1.0 / (L + lam * 8.0 / eps)
+    x = gradient.projected_gradient(A, AT, y, 20000, step, lam=lam, eps=eps)
+    Ad = A.toarray()
+    for b in range(y.shape[0]):
+        def f(v):
+            r = Ad @ v - y[b]
+            return r @ r + lam * gradient.tv(v.reshape(1, 5, 5), eps)[0]
+        res = minimize(f, np.zeros(25), method="L-BFGS-B", bounds=[(0, None)] * 25,
+                       options={"ftol": 1e-15, "gtol": 1e-10, "maxiter": 20000, "maxfun": 10**6})
+        assert f(x[b].ravel()) <= res.fun + 1e-7
+        np.testing.assert_allclose(x[b].ravel(), res.x, atol=2e-3)
