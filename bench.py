@@ -134,6 +134,7 @@ def main():
     import torch
 
     import paper_2009_07226_amd as xct
+    from paper_2009_07226_amd import gradient as pgrad
     from paper_2009_07226_amd import phantoms
 
     N, M, C, B = args.n, args.angles, args.n, args.batch
@@ -368,6 +369,21 @@ def main():
                        "fp16_vs_fp32_rel_l2_max": round(d16, 6),
                        "build_s_f16": round(A16.info()["build_seconds"], 3)}
         log(f"CGLS s/iter FP32 {t32 * 1e3:.3f} ms, FP16 {t16 * 1e3:.3f} ms")
+        # the generic gradient solver of Eq. (1) (x >= 0, TV) on the same
+        # FP16 operators: torch autograd around the projection pair
+        log("projected gradient FP16")
+        lam, eps, pg_it = 0.1, 0.05, 5
+        tau = 0.95 / pgrad.lipschitz(A16, lam, eps, 10)
+        pgrad.projected_gradient(A16, yc, 1, tau, lam=lam, eps=eps)
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        pgrad.projected_gradient(A16, yc, pg_it, tau, lam=lam, eps=eps)
+        g1.record()
+        torch.cuda.synchronize()
+        tpg = g0.elapsed_time(g1) * 1e-3 / pg_it
+        out["projected_gradient"] = {"iters": pg_it, "lam": lam, "eps": eps, "fp16_s_per_iter": round(tpg, 6),
+                                     "vs_spmm_pair": round(tpg / (ms16 * 1e-3), 3)}
         del A16
 
     if not args.no_cpu:

@@ -2,7 +2,8 @@
 hot path of parallel-beam XCT reconstruction (Hidayetoglu et al., SC20).
 
 The kernels live in libxct.so (C ABI: include/xct.h); this package is its
-thin binding plus seeded input generators.
+thin binding, the gradient solver of Eq. (1) built on it (``gradient``), and
+seeded input generators.
 """
 from .xct import (BF16, F16, F32, Matrix, XctBackproject, XctError, XctProject, backproject,
                   backproject_streamed, cgls, lib, library_loaded, profile_enable, profile_read, project,

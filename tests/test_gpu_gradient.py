@@ -1,0 +1,123 @@
+"""GPU parity of the generic gradient solver of Eq. (1) (non-negativity, TV)
+against the FP64 oracle, and properties at the full 1024^2 x 1500 geometry.
+
+Tolerance.  Each iteration maps x -> P_C(x - tau g(x)) with tau below 1 / L,
+a non-expansive map, so a per-iteration perturbation e (FP32 rounding of the
+two SpMMs and of the update: relative ~1e-6 of the step) adds up at most
+linearly: after k = 20 iterations the relative error stays below ~2e-5.  The
+tests allow 1e-4 for an FP32 matrix.  A 16-bit matrix perturbs the operator
+itself by up to 2^-11 per entry (FP16; 2^-8 for BF16); the iterate moves by
+about that fraction, so the tests allow 2e-3 (FP16) and 1.5e-2 (BF16).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import gradient as ograd
+from paper_2009_07226_amd import phantoms
+
+pytestmark = pytest.mark.gpu
+
+xct = pytest.importorskip("paper_2009_07226_amd")
+from paper_2009_07226_amd import gradient as pg  # noqa: E402
+
+_cache = {}
+
+
+def banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def setup(N, M, C, dt, B=3, seed=5):
+    key = (N, M, C)
+    if key not in _cache:
+        A = oracle.build_A(N, M, C)
+        _cache[key] = (A, oracle.build_AT(N, M, C), np.linalg.norm(A.toarray(), 2) ** 2)
+    A, AT, s2 = _cache[key]
+    x_true = phantoms.ellipse_batch(N, B, 6, seed).numpy().astype(np.float64)
+    y = oracle.project(A, x_true) + 0.05 * phantoms.noise((M * C,), range(B), seed + 1)
+    y32 = y.astype(np.float32)                       # both sides see the same sinogram values
+    G = xct.Matrix(N, M, C, dt)
+    return A, AT, s2, G, y32
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-4), ("f16", 2e-3), ("bf16", 1.5e-2)])
+@pytest.mark.parametrize("lam,nonneg", [(0.0, True), (0.5, True), (0.5, False)])
+def test_projected_gradient_matches_oracle(dt, tol, lam, nonneg):
+    N, M, C, iters, eps = 44, 30, 45, 20, 0.05
+    banner(f"projected gradient N={N} M={M} C={C} dt={dt} lam={lam} nonneg={nonneg}")
+    A, AT, s2, G, y32 = setup(N, M, C, dt)
+    L = 2.0 * s2 + 8.0 * lam / eps
+    tau = 0.9 / L
+    ref = ograd.projected_gradient(A, AT, y32.astype(np.float64), iters, tau, lam=lam, eps=eps, nonneg=nonneg)
+    y = torch.from_numpy(y32).reshape(-1, M, C).cuda()
+    x = pg.projected_gradient(G, y, iters, tau, lam=lam, eps=eps, nonneg=nonneg).cpu().numpy()
+    if nonneg:
+        assert x.min() >= 0.0
+        assert (ref == 0).any(), "constraint inactive: the case would not test the projection"
+    d = np.linalg.norm((x - ref).reshape(x.shape[0], -1), axis=1) / np.linalg.norm(ref.reshape(x.shape[0], -1), axis=1)
+    assert d.max() < tol, d
+
+
+def test_cost_and_tv_match_oracle():
+    N, M, C, eps, lam = 44, 30, 45, 0.05, 0.3
+    banner("cost / TV values")
+    A, AT, s2, G, y32 = setup(N, M, C, "f32")
+    x = phantoms.ellipse_batch(N, 3, 4, 9).numpy()
+    J = pg.cost(G, torch.from_numpy(x).cuda(), torch.from_numpy(y32).reshape(-1, M, C).cuda(), lam, eps)
+    ref = ograd.cost(A, x.astype(np.float64), y32.astype(np.float64), lam, eps)
+    np.testing.assert_allclose(J.cpu().numpy(), ref, rtol=1e-4)
+
+
+def test_per_slice_step_equals_separate_runs():
+    N, M, C = 44, 30, 45
+    banner("per-slice steps")
+    A, AT, s2, G, y32 = setup(N, M, C, "f32")
+    y = torch.from_numpy(y32).reshape(-1, M, C).cuda()
+    steps = torch.tensor([0.2, 0.5, 0.9]) / (2.0 * s2)
+    x = pg.projected_gradient(G, y, 8, steps.cuda())
+    for b in range(3):
+        xb = pg.projected_gradient(G, y[b:b + 1].contiguous(), 8, float(steps[b]))
+        torch.testing.assert_close(x[b:b + 1], xb, rtol=1e-5, atol=1e-6)
+
+
+def test_opnorm_and_lipschitz():
+    N, M, C = 44, 30, 45
+    banner("power iteration")
+    A, AT, s2, G, y32 = setup(N, M, C, "f32")
+    est = pg.opnorm_sq(G, 60)
+    assert 0.98 * s2 <= est <= s2 * (1 + 1e-5)
+    assert pg.lipschitz(G, 0.5, 0.05, 60) == pytest.approx(2.02 * est + 80.0, rel=1e-6)
+
+
+def test_argument_checks():
+    N, M, C = 16, 12, 16
+    G = xct.Matrix(N, M, C, "f32")
+    y = torch.zeros(2, M, C, device="cuda")
+    with pytest.raises(TypeError):
+        pg.projected_gradient(G, y.double(), 1, 0.1)
+    with pytest.raises(TypeError):
+        pg.projected_gradient(G, y.cpu(), 1, 0.1)
+    with pytest.raises(ValueError):
+        pg.projected_gradient(G, torch.zeros(2, M, C + 1, device="cuda"), 1, 0.1)
+    with pytest.raises(ValueError):
+        pg.projected_gradient(G, y, 1, 0.1, eps=0.0)
+    assert pg.projected_gradient(G, y, 0, 0.1).abs().max() == 0.0
+
+
+def test_full_geometry_cost_decreases():
+    """The 1024^2 x 1500 benchmark geometry (FP16 matrix, 4 slices): with tau below
+    1 / L the cost of every slice decreases at every step, and x stays >= 0.
+    The step comes from the power-iteration estimate padded by 1%."""
+    N, M, C, B, lam, eps = 1024, 1500, 1024, 4, 0.1, 0.05
+    banner(f"full geometry projected gradient B={B}")
+    G = xct.Matrix(N, M, C, "f16")
+    x_true = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device="cuda").float()
+    y = xct.project(G, x_true)
+    tau = 0.95 / pg.lipschitz(G, lam, eps, 20)
+    costs = []
+    x = pg.projected_gradient(G, y, 6, tau, lam=lam, eps=eps, costs=costs)
+    J = torch.stack(costs).numpy()
+    assert (np.diff(J, axis=0) < 0).all(), J
+    assert x.min().item() >= 0.0
