@@ -227,6 +227,34 @@ size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
 int xct_cgls(const xct_matrix *A, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
              void *workspace, double *resid, int32_t *status, void *stream);
 
+/* Device workspace needed by xct_projected_gradient for `batch` slices. */
+size_t xct_pgrad_workspace_bytes(const xct_matrix *A, int batch);
+
+/*
+ * Projected gradient descent on Eq. (1), ||y - A x||^2 + lam * TV_eps(x)
+ * over x in C, by the gradient loop of Sec. II (project, residual,
+ * backproject, update), every slice independently, `iters` iterations:
+ *   x <- P_C(x - step_b * (2 A^T (A x - y) + lam * grad TV_eps(x)))
+ * TV_eps(x) = sum over pixels of sqrt(dr^2 + dc^2 + eps^2), with forward
+ * differences dr = x[i+1][j] - x[i][j] and dc = x[i][j+1] - x[i][j] taken as
+ * 0 on the last row / column.  C is x >= 0 when nonneg != 0 (clamp at zero),
+ * else all x.  The paper leaves R, C and the step rule open; the step is
+ * the caller's (the cost decreases for step_b < 2 / L_b with
+ * L_b <= 2 ||A||^2 + 8 lam / eps).
+ *   y          device, [batch][n_angles][n_channels] FP32
+ *   x          device, [batch][n][n] FP32: the start point on entry, the
+ *              last iterate on return
+ *   step       device, [batch] FP32 per-slice step lengths
+ *   lam, eps   lam >= 0, eps > 0
+ *   workspace  device, >= xct_pgrad_workspace_bytes(A, batch) bytes, 256-B aligned
+ * Each iteration is one projection and one backprojection (the operands of
+ * a 16-bit matrix are max-norm scaled and rounded as in xct_project), a
+ * residual pass and one fused TV / step / clamp pass.  Enqueued on
+ * `stream`; no host sync.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ */
+int xct_projected_gradient(const xct_matrix *A, const float *y, float *x, int batch, int iters,
+                           const float *step, float lam, float eps, int nonneg, void *workspace, void *stream);
+
 /*
  * Decode one operator back to coordinate form on the host, in storage
  * order (for tests and tools).  which = 0: A (row = k*n_channels + c,

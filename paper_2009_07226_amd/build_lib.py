@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxct.so")
-SOURCES = ["build.hip", "spmm.hip", "cgls.hip", "util.hip", "stream.hip"]
+SOURCES = ["build.hip", "spmm.hip", "cgls.hip", "util.hip", "stream.hip", "gradient.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,136 @@
+// Projected gradient descent on Eq. (1), ||y - A x||^2 + lam * TV_eps(x)
+// over x in C, with the gradient loop of Sec. II: project the estimate, form
+// the residual, backproject it (the data gradient is 2 A^T (A x - y)), update.
+// C is the non-negative orthant (clamp at zero) or the whole space; TV_eps is
+// the smoothed isotropic total variation, sum over pixels of
+// sqrt(dr^2 + dc^2 + eps^2) with forward differences dr (down the rows) and
+// dc (along a row) that are zero past the last row and column.
+//
+// Per iteration: one projection and one backprojection (the staged SpMM),
+// one residual pass over the sinograms, and one fused pass over the volume
+// that evaluates the TV gradient from a 3 x 3 neighbourhood, takes the step
+// and clamps.  The volume update is out of place (the stencil reads the old
+// iterate), so the iterate alternates between the caller's buffer and one in
+// the workspace.
+#include <algorithm>
+#include <utility>
+
+#include "common.hpp"
+
+namespace xct {
+
+static size_t align256g(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct PgWs {
+    float *q, *s, *xalt;
+    void *spmm;
+};
+
+// q = A x and r = q - y (in place) [B][M*C]; s = A^T r [B][N*N]; the other
+// iterate buffer [B][N*N]; then the SpMM workspace.
+static size_t pg_ws_layout(const xct_matrix *m, int batch, char *base, PgWs *w) {
+    const size_t vol = align256g((size_t)batch * m->n * m->n * sizeof(float));
+    const size_t sino = align256g((size_t)batch * m->M * m->C * sizeof(float));
+    if (w) {
+        w->q = (float *)base;
+        w->s = (float *)(base + sino);
+        w->xalt = (float *)(base + sino + vol);
+        w->spmm = base + sino + 2 * vol;
+    }
+    return sino + 2 * vol + spmm_workspace(m, batch);
+}
+
+__global__ void __launch_bounds__(256) k_residual(float *__restrict__ q, const float *__restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) q[i] = q[i] - y[i];
+}
+
+// Forward differences at (i, j) of one N x N slice; zero past the last row /
+// column.  Returns (dr, dc) and the smoothed magnitude m.
+__device__ __forceinline__ float tv_term(const float *__restrict__ x, int N, int i, int j, float eps2, float &dr,
+                                         float &dc) {
+    const float c = x[(int64_t)i * N + j];
+    dr = i + 1 < N ? x[(int64_t)(i + 1) * N + j] - c : 0.0f;
+    dc = j + 1 < N ? x[(int64_t)i * N + j + 1] - c : 0.0f;
+    return sqrtf(dr * dr + dc * dc + eps2);
+}
+
+// x_out = P_C(x - tau_b (2 s + lam grad TV_eps(x))).  Pixel (i, j) enters dr
+// and dc at itself with sign -1, dr at (i-1, j) and dc at (i, j-1) with +1.
+// One thread per pixel; a row of the slice is contiguous, so neighbouring
+// threads read neighbouring words and the row above / below come from cache.
+__global__ void __launch_bounds__(256) k_pg_update(const float *__restrict__ x, const float *__restrict__ s,
+                                                   float *__restrict__ xo, const float *__restrict__ tau, int N,
+                                                   int64_t n_total, float lam, float eps2, int nonneg) {
+    const int64_t nn = (int64_t)N * N;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_total; p += stride) {
+        const int64_t b = p / nn;
+        const int64_t v = p - b * nn;
+        const int i = (int)(v / N), j = (int)(v - (int64_t)i * N);
+        const float *xs = x + b * nn;
+        float g = 2.0f * s[p];
+        if (lam != 0.0f) {
+            float dr, dc;
+            const float m0 = tv_term(xs, N, i, j, eps2, dr, dc);
+            float t = -(dr + dc) / m0;
+            if (i > 0) {
+                float dr1, dc1;
+                const float m1 = tv_term(xs, N, i - 1, j, eps2, dr1, dc1);
+                t += dr1 / m1;
+            }
+            if (j > 0) {
+                float dr2, dc2;
+                const float m2 = tv_term(xs, N, i, j - 1, eps2, dr2, dc2);
+                t += dc2 / m2;
+            }
+            g += lam * t;
+        }
+        float xn = x[p] - tau[b] * g;
+        if (nonneg) xn = fmaxf(xn, 0.0f);
+        xo[p] = xn;
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)std::min<int64_t>(g, 8 * 256 * 16);
+}
+
+}  // namespace xct
+
+using namespace xct;
+
+extern "C" size_t xct_pgrad_workspace_bytes(const xct_matrix *m, int batch) {
+    if (!m || batch < 1) return 0;
+    return pg_ws_layout(m, batch, nullptr, nullptr);
+}
+
+extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float *x, int batch, int iters,
+                                      const float *step, float lam, float eps, int nonneg, void *workspace,
+                                      void *stream) {
+    if (!m || !y || !x || !step || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
+    if (iters < 0) return fail(XCT_ERR_INVALID, "iters must be >= 0");
+    if (!(lam >= 0.0f) || !(eps > 0.0f)) return fail(XCT_ERR_INVALID, "need lam >= 0 and eps > 0");
+    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
+    PgWs w;
+    pg_ws_layout(m, batch, (char *)workspace, &w);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n_vol = (int64_t)batch * m->n * m->n, n_sino = (int64_t)batch * m->M * m->C;
+    float *cur = x, *nxt = w.xalt;
+    for (int k = 0; k < iters; ++k) {
+        int rc = spmm_call(m, 0, cur, w.q, batch, XCT_F32, w.spmm, stream);
+        if (rc != XCT_OK) return rc;
+        hipLaunchKernelGGL(k_residual, dim3(grid_for(n_sino)), dim3(256), 0, st, w.q, y, n_sino);
+        XCT_HIP_TRY(hipGetLastError());
+        rc = spmm_call(m, 1, w.q, w.s, batch, XCT_F32, w.spmm, stream);
+        if (rc != XCT_OK) return rc;
+        hipLaunchKernelGGL(k_pg_update, dim3(grid_for(n_vol)), dim3(256), 0, st, cur, w.s, nxt, step, m->n, n_vol,
+                           lam, eps * eps, nonneg ? 1 : 0);
+        XCT_HIP_TRY(hipGetLastError());
+        std::swap(cur, nxt);
+    }
+    if (cur != x) XCT_HIP_TRY(hipMemcpyAsync(x, cur, (size_t)n_vol * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return XCT_OK;
+}

@@ -3,10 +3,11 @@
 Eq. (1) minimises ||y - A x||^2 + R(x) over x in a constraint set C, and
 Sec. II describes the loop that solves it: project the estimate, form the
 residual against the sinogram, backproject it to obtain the gradient, update.
-Here the gradient comes from torch autograd through ``XctProject``, so each
-iteration runs one projection and one backprojection in ``libxct.so``; the
-regulariser, its gradient and the update are small elementwise passes over the
-(B, N, N) estimate.
+``projected_gradient`` runs the whole loop in ``libxct.so``: per iteration one
+projection, one backprojection, a residual pass and one fused pass that
+evaluates the TV gradient, takes the step and clamps.  ``cost`` and ``tv`` are
+the same objective written with torch autograd through ``XctProject``, for
+callers who build their own objectives on the operator pair.
 
 Choices where the paper names none: C is the non-negative orthant (clamp at
 zero) or the whole space; R(x) = lam * TV_eps(x), the smoothed isotropic total
@@ -25,6 +26,7 @@ import torch
 import torch.nn.functional as Fn
 
 from .xct import Matrix, XctProject, backproject, project
+from .xct import projected_gradient as _native_pg
 
 
 def tv(x: torch.Tensor, eps: float) -> torch.Tensor:
@@ -43,40 +45,16 @@ def cost(A: Matrix, x: torch.Tensor, y: torch.Tensor, lam: float = 0.0, eps: flo
 
 def projected_gradient(A: Matrix, y: torch.Tensor, iters: int, step: Union[float, torch.Tensor],
                        lam: float = 0.0, eps: float = 1e-2, nonneg: bool = True,
-                       x0: Optional[torch.Tensor] = None, costs: Optional[list] = None) -> torch.Tensor:
-    """Projected gradient descent on Eq. (1) for a batch of sinograms.
+                       x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Projected gradient descent on Eq. (1) for a batch of sinograms, run
+    entirely in ``libxct.so`` (``xct_projected_gradient``): each iteration
+    takes x <- P_C(x - step * g) with g the gradient of ``cost``.
 
     y: (B, n_angles, n_channels) FP32 on the matrix's GPU.  step: a float, or a
-    (B,) tensor of per-slice steps.  Each iteration takes x <- P_C(x - step * g)
-    with g the gradient of ``cost``.  When ``costs`` is a list, the per-slice
-    cost of each iterate before its update is appended to it (one host sync per
-    iteration).  Returns x (B, n, n) FP32."""
+    (B,) tensor of per-slice steps.  Returns x (B, n, n) FP32."""
     if not isinstance(y, torch.Tensor) or y.dtype != torch.float32 or y.dim() != 3 or not y.is_cuda:
         raise TypeError("y must be a 3-D float32 CUDA tensor (B, n_angles, n_channels)")
-    if tuple(y.shape[1:]) != A.sino_shape:
-        raise ValueError(f"y has shape {tuple(y.shape)}, expected (B, {A.sino_shape[0]}, {A.sino_shape[1]})")
-    if iters < 0 or eps <= 0.0 or lam < 0.0:
-        raise ValueError("need iters >= 0, eps > 0 and lam >= 0")
-    B = y.shape[0]
-    y = y.contiguous()
-    if x0 is None:
-        x = torch.zeros((B,) + A.vol_shape, dtype=torch.float32, device=y.device)
-    else:
-        if x0.shape != (B,) + A.vol_shape or x0.dtype != torch.float32:
-            raise ValueError("x0 must be float32 of shape (B, n, n)")
-        x = x0.detach().clone()
-    tau = step.reshape(B, 1, 1).to(x) if isinstance(step, torch.Tensor) else float(step)
-    for _ in range(iters):
-        x.requires_grad_(True)
-        J = cost(A, x, y, lam, eps)
-        (g,) = torch.autograd.grad(J.sum(), x)
-        if costs is not None:
-            costs.append(J.detach().cpu())
-        with torch.no_grad():
-            x = x.detach() - tau * g
-            if nonneg:
-                x.clamp_(min=0.0)
-    return x.detach()
+    return _native_pg(A, y.contiguous(), iters, step, lam=lam, eps=eps, nonneg=nonneg, x0=x0)
 
 
 def opnorm_sq(A: Matrix, iters: int = 30, seed: int = 0) -> float:

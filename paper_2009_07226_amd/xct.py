@@ -99,6 +99,10 @@ def lib():
     L.xct_project_streamed.restype = i
     L.xct_backproject_streamed.argtypes = [vp, vp, vp, i, i, i, vp, vp, vp, vp]
     L.xct_backproject_streamed.restype = i
+    L.xct_pgrad_workspace_bytes.argtypes = [vp, i]
+    L.xct_pgrad_workspace_bytes.restype = sz
+    L.xct_projected_gradient.argtypes = [vp, vp, vp, i, i, vp, ctypes.c_float, ctypes.c_float, i, vp, vp]
+    L.xct_projected_gradient.restype = i
     L.xct_last_error.argtypes = []
     L.xct_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -316,6 +320,39 @@ def cgls(A: Matrix, y: torch.Tensor, iters: int, out: Optional[torch.Tensor] = N
                           workspace.data_ptr(), resid.ctypes.data if want_resid else None,
                           status.ctypes.data if want_resid else None, _stream()))
     return out, resid, status
+
+
+def projected_gradient(A: Matrix, y: torch.Tensor, iters: int, step, lam: float = 0.0, eps: float = 1e-2,
+                       nonneg: bool = True, x0: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Projected gradient descent on ||y - A x||^2 + lam * TV_eps(x) over x >= 0
+    (or all x when ``nonneg`` is False), `iters` iterations from x0 (zero when
+    None).  y: (B, n_angles, n_channels) FP32; step: a float or a (B,) tensor of
+    per-slice steps.  Returns x (B, n, n) FP32 (``out`` when given)."""
+    B = y.shape[0] if y.dim() == 3 else -1
+    _require(y, (B,) + A.sino_shape, "y", torch.float32)
+    if iters < 0 or not eps > 0.0 or not lam >= 0.0:
+        raise ValueError("need iters >= 0, eps > 0 and lam >= 0")
+    if out is None:
+        out = torch.empty((B,) + A.vol_shape, dtype=torch.float32, device=y.device)
+    _require(out, (B,) + A.vol_shape, "out", torch.float32)
+    if x0 is None:
+        out.zero_()
+    else:
+        _require(x0, (B,) + A.vol_shape, "x0", torch.float32)
+        if x0.data_ptr() != out.data_ptr():
+            out.copy_(x0)
+    if isinstance(step, torch.Tensor):
+        tau = step.to(device=y.device, dtype=torch.float32).reshape(-1).contiguous()
+        if tau.numel() != B:
+            raise ValueError(f"step has {tau.numel()} entries, expected {B}")
+    else:
+        tau = torch.full((B,), float(step), dtype=torch.float32, device=y.device)
+    if workspace is None:
+        workspace = torch.empty(lib().xct_pgrad_workspace_bytes(A.handle, B), dtype=torch.uint8, device=y.device)
+    _check(lib().xct_projected_gradient(A.handle, y.data_ptr(), out.data_ptr(), B, int(iters), tau.data_ptr(),
+                                        float(lam), float(eps), 1 if nonneg else 0, workspace.data_ptr(), _stream()))
+    return out
 
 
 def profile_enable(on: bool = True) -> None:

@@ -46,6 +46,9 @@ def test_argument_errors_without_device():
     assert L.xct_project_streamed(None, None, None, 1, 1, 0, None, None, None, None) == -1
     assert L.xct_backproject_streamed(None, None, None, 1, 1, 0, None, None, None, None) == -1
     assert L.xct_cgls_workspace_bytes(None, 4, 3) == 0
+    assert L.xct_pgrad_workspace_bytes(None, 4) == 0
+    assert L.xct_projected_gradient(None, None, None, 1, 1, None, 0.0, 0.1, 1, None, None) == -1
+    assert b"NULL" in L.xct_last_error()
     g = ctypes.c_double()
     assert L.xct_read_bandwidth(None, 1 << 20, 1, ctypes.byref(g), None) == -1
     assert L.xct_profile_read(None, None) == -1
