@@ -13,6 +13,7 @@
 // iterate), so the iterate alternates between the caller's buffer and one in
 // the workspace.
 #include <algorithm>
+#include <climits>
 #include <utility>
 
 #include "common.hpp"
@@ -57,39 +58,43 @@ __device__ __forceinline__ float tv_term(const float *__restrict__ x, int N, int
 
 // x_out = P_C(x - tau_b (2 s + lam grad TV_eps(x))).  Pixel (i, j) enters dr
 // and dc at itself with sign -1, dr at (i-1, j) and dc at (i, j-1) with +1.
-// One thread per pixel; a row of the slice is contiguous, so neighbouring
-// threads read neighbouring words and the row above / below come from cache.
+// One workgroup per 256-column segment of one row of one slice.  Workgroups
+// are dealt round-robin to the 8 XCDs, so the linear id is remapped to give
+// each XCD a contiguous range of (slice, row, segment): the rows above and
+// below a segment are then mostly read by the same XCD and hit its L2.
 __global__ void __launch_bounds__(256) k_pg_update(const float *__restrict__ x, const float *__restrict__ s,
                                                    float *__restrict__ xo, const float *__restrict__ tau, int N,
-                                                   int64_t n_total, float lam, float eps2, int nonneg) {
-    const int64_t nn = (int64_t)N * N;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_total; p += stride) {
-        const int64_t b = p / nn;
-        const int64_t v = p - b * nn;
-        const int i = (int)(v / N), j = (int)(v - (int64_t)i * N);
-        const float *xs = x + b * nn;
-        float g = 2.0f * s[p];
-        if (lam != 0.0f) {
-            float dr, dc;
-            const float m0 = tv_term(xs, N, i, j, eps2, dr, dc);
-            float t = -(dr + dc) / m0;
-            if (i > 0) {
-                float dr1, dc1;
-                const float m1 = tv_term(xs, N, i - 1, j, eps2, dr1, dc1);
-                t += dr1 / m1;
-            }
-            if (j > 0) {
-                float dr2, dc2;
-                const float m2 = tv_term(xs, N, i, j - 1, eps2, dr2, dc2);
-                t += dc2 / m2;
-            }
-            g += lam * t;
+                                                   int nseg, int nblocks, float lam, float eps2, int nonneg) {
+    int L = blockIdx.x;
+    if ((nblocks & 7) == 0) L = (L & 7) * (nblocks >> 3) + (L >> 3);
+    const int seg = L % nseg;
+    const int r = L / nseg;            // b * N + i
+    const int i = r % N;
+    const int b = r / N;
+    const int j = seg * 256 + (int)threadIdx.x;
+    if (j >= N) return;
+    const float *xs = x + (int64_t)b * N * N;
+    const int64_t p = (int64_t)r * N + j;
+    float g = 2.0f * s[p];
+    if (lam != 0.0f) {
+        float dr, dc;
+        const float m0 = tv_term(xs, N, i, j, eps2, dr, dc);
+        float t = -(dr + dc) / m0;
+        if (i > 0) {
+            float dr1, dc1;
+            const float m1 = tv_term(xs, N, i - 1, j, eps2, dr1, dc1);
+            t += dr1 / m1;
         }
-        float xn = x[p] - tau[b] * g;
-        if (nonneg) xn = fmaxf(xn, 0.0f);
-        xo[p] = xn;
+        if (j > 0) {
+            float dr2, dc2;
+            const float m2 = tv_term(xs, N, i, j - 1, eps2, dr2, dc2);
+            t += dc2 / m2;
+        }
+        g += lam * t;
     }
+    float xn = x[p] - tau[b] * g;
+    if (nonneg) xn = fmaxf(xn, 0.0f);
+    xo[p] = xn;
 }
 
 static unsigned grid_for(int64_t n) {
@@ -118,6 +123,9 @@ extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float
     pg_ws_layout(m, batch, (char *)workspace, &w);
     hipStream_t st = (hipStream_t)stream;
     const int64_t n_vol = (int64_t)batch * m->n * m->n, n_sino = (int64_t)batch * m->M * m->C;
+    const int nseg = (m->n + 255) / 256;
+    const int64_t nblocks = (int64_t)nseg * m->n * batch;
+    if (nblocks > INT32_MAX) return fail(XCT_ERR_INVALID, "batch too large for one call");
     float *cur = x, *nxt = w.xalt;
     for (int k = 0; k < iters; ++k) {
         int rc = spmm_call(m, 0, cur, w.q, batch, XCT_F32, w.spmm, stream);
@@ -126,8 +134,8 @@ extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float
         XCT_HIP_TRY(hipGetLastError());
         rc = spmm_call(m, 1, w.q, w.s, batch, XCT_F32, w.spmm, stream);
         if (rc != XCT_OK) return rc;
-        hipLaunchKernelGGL(k_pg_update, dim3(grid_for(n_vol)), dim3(256), 0, st, cur, w.s, nxt, step, m->n, n_vol,
-                           lam, eps * eps, nonneg ? 1 : 0);
+        hipLaunchKernelGGL(k_pg_update, dim3((unsigned)nblocks), dim3(256), 0, st, cur, w.s, nxt, step, m->n, nseg,
+                           (int)nblocks, lam, eps * eps, nonneg ? 1 : 0);
         XCT_HIP_TRY(hipGetLastError());
         std::swap(cur, nxt);
     }
