@@ -46,51 +46,76 @@ __global__ void __launch_bounds__(256) k_residual(float *__restrict__ q, const f
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) q[i] = q[i] - y[i];
 }
 
-// x_out = P_C(x - tau_b (2 s + lam grad TV_eps(x))).  Pixel (i, j) enters dr
-// and dc at itself with sign -1, dr at (i-1, j) and dc at (i, j-1) with +1.
-// One workgroup per 256-column segment of one row of one slice.  Workgroups
-// are dealt round-robin to the 8 XCDs, so the linear id is remapped to give
-// each XCD a contiguous range of (slice, row, segment): the rows above and
-// below a segment are then mostly read by the same XCD and hit its L2.
+// Rows of one column handled by one thread of k_pg_update.
+constexpr int kPgRows = 4;
+
+// x_out = P_C(x - tau_b (2 s + lam grad TV_eps(x))).  With u = dr / m and
+// v = dc / m at a pixel (m = sqrt(dr^2 + dc^2 + eps^2)), the TV gradient at
+// (i, j) is -(u + v)(i, j) + u(i-1, j) + v(i, j-1).
+// One thread per column and kPgRows consecutive rows; one workgroup per
+// 256-column segment of a kPgRows-row strip of one slice.  Every load of the
+// strip (rows i0-1 .. i0+kPgRows at columns j-1, j, j+1, clamped into the
+// slice) is issued before any arithmetic, so each wave waits for memory once
+// per kPgRows rows, and u of the row above is carried from the previous row.
+// Workgroups are dealt round-robin to the 8 XCDs, so the linear id is
+// remapped to give each XCD a contiguous range of (slice, strip, segment):
+// the rows just above and below a strip are then read by the same XCD.
 __global__ void __launch_bounds__(256) k_pg_update(const float *__restrict__ x, const float *__restrict__ s,
                                                    float *__restrict__ xo, const float *__restrict__ tau, int N,
-                                                   int nseg, int nblocks, float lam, float eps2, int nonneg) {
+                                                   int nseg, int nstrip, int nblocks, float lam, float eps2,
+                                                   int nonneg) {
+    constexpr int R = kPgRows;
     int L = blockIdx.x;
     if ((nblocks & 7) == 0) L = (L & 7) * (nblocks >> 3) + (L >> 3);
     const int seg = L % nseg;
-    const int r = L / nseg;            // b * N + i
-    const int i = r % N;
-    const int b = r / N;
+    const int q = L / nseg;  // b * nstrip + strip
+    const int i0 = (q % nstrip) * R;
+    const int b = q / nstrip;
     const int j = seg * 256 + (int)threadIdx.x;
     if (j >= N) return;
-    const float *xs = x + (int64_t)b * N * N;
-    const int64_t p = (int64_t)r * N + j;
-    // Every load is issued before any arithmetic (neighbour indices clamped
-    // into the slice), so one wave waits for memory once, not once per term.
-    const bool up = i > 0, left = j > 0, down = i + 1 < N, right = j + 1 < N;
-    const int im = up ? i - 1 : i, ip = down ? i + 1 : i;
+    const bool left = j > 0, right = j + 1 < N;
     const int jm = left ? j - 1 : j, jp = right ? j + 1 : j;
-    const float sp = s[p], tb = tau[b];
-    const float c = xs[(int64_t)i * N + j];
-    const float xd = xs[(int64_t)ip * N + j], xr = xs[(int64_t)i * N + jp];
-    const float xu = xs[(int64_t)im * N + j], xur = xs[(int64_t)im * N + jp];
-    const float xl = xs[(int64_t)i * N + jm], xdl = xs[(int64_t)ip * N + jm];
-    // Branch-free: every term is computed from the clamped values (finite,
-    // as eps2 > 0) and the edge rules select it; lam = 0 adds 0 * t = 0.
-    // term of (i, j): dr = x[i+1][j] - x[i][j], dc = x[i][j+1] - x[i][j]
-    const float dr0 = down ? xd - c : 0.0f, dc0 = right ? xr - c : 0.0f;
-    const float t0 = -(dr0 + dc0) / sqrtf(dr0 * dr0 + dc0 * dc0 + eps2);
-    // term of (i-1, j): its dr is x[i][j] - x[i-1][j]
-    const float dr1 = c - xu, dc1 = right ? xur - xu : 0.0f;
-    const float t1 = dr1 / sqrtf(dr1 * dr1 + dc1 * dc1 + eps2);
-    // term of (i, j-1): its dc is x[i][j] - x[i][j-1]
-    const float dr2 = down ? xdl - xl : 0.0f, dc2 = c - xl;
-    const float t2 = dc2 / sqrtf(dr2 * dr2 + dc2 * dc2 + eps2);
-    const float t = t0 + (up ? t1 : 0.0f) + (left ? t2 : 0.0f);
-    const float g = 2.0f * sp + lam * t;
-    float xn = c - tb * g;
-    if (nonneg) xn = fmaxf(xn, 0.0f);
-    xo[p] = xn;
+    const float *xs = x + (int64_t)b * N * N;
+    auto row = [&](int i) { return xs + (int64_t)min(max(i, 0), N - 1) * N; };
+    // cj[k], cr[k]: rows i0-1+k at columns j, j+1; cl[k]: row i0+k at column j-1.
+    float cj[R + 2], cr[R + 1], cl[R + 1], sp[R];
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) cj[k] = row(i0 - 1 + k)[j];
+#pragma unroll
+    for (int k = 0; k < R + 1; ++k) cr[k] = row(i0 - 1 + k)[jp];
+#pragma unroll
+    for (int k = 0; k < R + 1; ++k) cl[k] = row(i0 + k)[jm];
+    const int64_t p0 = ((int64_t)b * N + i0) * N + j;
+    const float *ss = s + (int64_t)b * N * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) sp[r] = ss[(int64_t)min(i0 + r, N - 1) * N + j];  // rows past N unused
+    const float tb = tau[b];
+    // u at row i0-1 (used only when i0 > 0, where its dr is x[i0][j] - x[i0-1][j])
+    float u_up;
+    {
+        const float dr = cj[1] - cj[0], dc = right ? cr[0] - cj[0] : 0.0f;
+        u_up = dr / sqrtf(dr * dr + dc * dc + eps2);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = i0 + r;
+        const bool up = i > 0, down = i + 1 < N;
+        const float c = cj[r + 1];
+        // (i, j): dr = x[i+1][j] - x[i][j], dc = x[i][j+1] - x[i][j]
+        const float dr0 = down ? cj[r + 2] - c : 0.0f, dc0 = right ? cr[r + 1] - c : 0.0f;
+        const float m0 = sqrtf(dr0 * dr0 + dc0 * dc0 + eps2);
+        const float u0 = dr0 / m0, v0 = dc0 / m0;
+        // (i, j-1): dr = x[i+1][j-1] - x[i][j-1], dc = x[i][j] - x[i][j-1]
+        const float dr2 = down ? cl[r + 1] - cl[r] : 0.0f, dc2 = c - cl[r];
+        const float v2 = dc2 / sqrtf(dr2 * dr2 + dc2 * dc2 + eps2);
+        // Branch-free: every term is finite (eps2 > 0) and the edge rules
+        // select it; lam = 0 adds 0 * t = 0.
+        const float t = -(u0 + v0) + (up ? u_up : 0.0f) + (left ? v2 : 0.0f);
+        float xn = c - tb * (2.0f * sp[r] + lam * t);
+        if (nonneg) xn = fmaxf(xn, 0.0f);
+        if (i < N) xo[p0 + (int64_t)r * N] = xn;
+        u_up = u0;
+    }
 }
 
 static unsigned grid_for(int64_t n) {
@@ -120,7 +145,8 @@ extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float
     hipStream_t st = (hipStream_t)stream;
     const int64_t n_vol = (int64_t)batch * m->n * m->n, n_sino = (int64_t)batch * m->M * m->C;
     const int nseg = (m->n + 255) / 256;
-    const int64_t nblocks = (int64_t)nseg * m->n * batch;
+    const int nstrip = (m->n + kPgRows - 1) / kPgRows;
+    const int64_t nblocks = (int64_t)nseg * nstrip * batch;
     if (nblocks > INT32_MAX) return fail(XCT_ERR_INVALID, "batch too large for one call");
     float *cur = x, *nxt = w.xalt;
     for (int k = 0; k < iters; ++k) {
@@ -131,7 +157,7 @@ extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float
         rc = spmm_call(m, 1, w.q, w.s, batch, XCT_F32, w.spmm, stream);
         if (rc != XCT_OK) return rc;
         hipLaunchKernelGGL(k_pg_update, dim3((unsigned)nblocks), dim3(256), 0, st, cur, w.s, nxt, step, m->n, nseg,
-                           (int)nblocks, lam, eps * eps, nonneg ? 1 : 0);
+                           nstrip, (int)nblocks, lam, eps * eps, nonneg ? 1 : 0);
         XCT_HIP_TRY(hipGetLastError());
         std::swap(cur, nxt);
     }
