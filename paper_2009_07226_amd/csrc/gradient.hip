@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_residual(float *__restrict__ q, const f
 }
 
 // Rows of one column handled by one thread of k_pg_update.
-constexpr int kPgRows = 4;
+constexpr int kPgRows = 8;
 
 // x_out = P_C(x - tau_b (2 s + lam grad TV_eps(x))).  With u = dr / m and
 // v = dc / m at a pixel (m = sqrt(dr^2 + dc^2 + eps^2)), the TV gradient at

@@ -113,7 +113,7 @@ def test_argument_checks():
 def test_native_step_matches_autograd_step():
     """One native iteration against the same step taken with torch autograd
     through XctProject (the TV term written independently in torch), at a
-    size with a ragged tail of 8 x 8 tiles and of the update's 4-row strips."""
+    size with a ragged tail of 8 x 8 tiles and of the update's 8-row strips."""
     N, M, C, lam, eps = 62, 37, 61, 0.4, 0.05
     banner("native step vs autograd step")
     G = xct.Matrix(N, M, C, "f32")
