@@ -24,8 +24,9 @@ gradient is 2 A^T (A x - y).
 
 Pins (tests/test_oracle_pins.py): the TV gradient against central finite
 differences of TV itself; the solver with lam = 0 against scipy's NNLS
-active-set solution, and with lam > 0 against L-BFGS-B (with bounds) applied
-to the cost evaluated straight from its definition.
+active-set solution, without the constraint against Landweber's closed form
+in the SVD basis after k steps, and with lam > 0 against L-BFGS-B (with
+bounds) applied to the cost evaluated straight from its definition.
 """
 from __future__ import annotations
 
