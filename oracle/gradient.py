@@ -22,8 +22,10 @@ readings are taken:
 The cost is taken exactly as Eq. (1) writes it (no factor 1/2), so its data
 gradient is 2 A^T (A x - y).
 
-Pins (tests/test_oracle_pins.py): the TV gradient against central finite
-differences of TV itself; the solver with lam = 0 against scipy's NNLS
+Pins (tests/test_oracle_pins.py): TV_eps and its gradient on a 2 x 3 image
+against values derived by hand (tests/golden/tv_eps_2x3.txt: stencil,
+orientation and boundary rule), and against the same on the transposed image;
+the TV gradient against central finite differences of TV itself; the solver with lam = 0 against scipy's NNLS
 active-set solution, without the constraint against Landweber's closed form
 in the SVD basis after k steps, and with lam > 0 against L-BFGS-B (with
 bounds) applied to the cost evaluated straight from its definition.

@@ -17,6 +17,7 @@ Each pin targets a different plausible mistake:
 """
 import math
 import os
+import re
 
 import numpy as np
 import pytest
@@ -334,6 +335,54 @@ def test_tv_gradient_matches_finite_differences():
     c = np.full((1, 4, 4), 2.5)
     assert gradient.tv(c, eps)[0] == pytest.approx(16 * eps)
     assert np.abs(gradient.tv_grad(c, eps)).max() == 0.0
+
+
+def _golden_tv():
+    """Parse tests/golden/tv_eps_2x3.txt: image, eps, and the hand-derived
+    TV_eps value and gradient as sums of coef*sqrt(k) / coef/sqrt(k) terms."""
+    def value(expr):
+        total = 0.0
+        for sign, coef, op, k in re.findall(r"([+-]?)\s*(\d+)\s*([*/])\s*sqrt\((\d+)\)", expr):
+            t = int(coef) * math.sqrt(int(k)) if op == "*" else int(coef) / math.sqrt(int(k))
+            total += -t if sign == "-" else t
+        return total
+    shape = eps = x = tv = None
+    grad = {}
+    for line in open(os.path.join(GOLDEN, "tv_eps_2x3.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, _, rest = line.partition(" ")
+        if key == "shape":
+            shape = tuple(int(v) for v in rest.split())
+        elif key == "eps":
+            eps = float(rest)
+        elif key == "x":
+            x = np.array([float(v) for v in rest.split()])
+        elif key == "tv":
+            tv = value(rest.split("=", 1)[1])
+        elif key == "g":
+            ij, expr = rest.split("=", 1)
+            i, j = (int(v) for v in ij.split())
+            grad[(i, j)] = value(expr)
+    g = np.zeros(shape)
+    for (i, j), v in grad.items():
+        g[i, j] = v
+    return x.reshape(shape), eps, tv, g
+
+
+def test_tv_matches_hand_derived_golden():
+    """TV_eps and its gradient on a 2 x 3 image derived by hand (forward
+    differences, zero past the last row and column): fixes the stencil, the
+    orientation of rows against columns and the boundary rule, which the
+    finite-difference check of tv_grad against tv cannot."""
+    from oracle import gradient
+    x, eps, tv_ref, g_ref = _golden_tv()
+    assert gradient.tv(x[None], eps)[0] == pytest.approx(tv_ref, rel=1e-14)
+    np.testing.assert_allclose(gradient.tv_grad(x[None], eps)[0], g_ref, rtol=1e-13, atol=1e-14)
+    # the transposed image has the same total variation (the regulariser is
+    # isotropic and its boundary rule symmetric), and the transposed gradient
+    assert gradient.tv(x.T[None].copy(), eps)[0] == pytest.approx(tv_ref, rel=1e-14)
+    np.testing.assert_allclose(gradient.tv_grad(x.T[None].copy(), eps)[0], g_ref.T, rtol=1e-13, atol=1e-14)
 
 
 def _nn_problem(N=6, M=8, C=6, seed=3):
