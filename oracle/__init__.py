@@ -17,7 +17,10 @@ grid, axis-aligned rays, voxel-aligned rectangles, disc projections under
 refinement, a hand-derived 2x2 example, brute force over all ray/voxel
 pairs, the adjoint identity between the ray-driven and the voxel-driven
 builds, rotation/reflection symmetries, and CGLS against Krylov least
-squares by dense QR and against the minimum-norm lstsq solution.
+squares by dense QR and against the minimum-norm lstsq solution; the
+per-iteration history (``cgls(..., history=True)``) and the A-only form for
+scans too large for both matrices (``TracedA``: A^T as A's transposed
+product) against the same Krylov solutions.
 """
 from __future__ import annotations
 
@@ -69,8 +72,19 @@ def _load():
     lib.oracle_csr_spmm.argtypes = [L, _i64p, _i32p, _f64p, L, I, _f64p, _f64p]
     lib.oracle_project_rows.argtypes = [I, I, I, I, _f64p, L, _i64p, _f64p]
     lib.oracle_backproject_voxels.argtypes = [I, I, I, I, _f64p, L, _i64p, _f64p]
+    _f64p_or_null = ctypes.c_void_p
     lib.oracle_cgls.argtypes = [L, _i64p, _i32p, _f64p, L, _i64p, _i32p, _f64p,
-                                I, _f64p, I, _f64p, _f64p, _intp]
+                                I, _f64p, I, _f64p, _f64p, _intp, _f64p_or_null]
+    lib.oracle_traced_build.argtypes = [I, I, I]
+    lib.oracle_traced_build.restype = ctypes.c_void_p
+    lib.oracle_traced_nnz.argtypes = [ctypes.c_void_p]
+    lib.oracle_traced_nnz.restype = L
+    lib.oracle_traced_project.argtypes = [ctypes.c_void_p, I, _f64p, _f64p]
+    lib.oracle_traced_project.restype = None
+    lib.oracle_traced_cgls.argtypes = [ctypes.c_void_p, I, _f64p, I, _f64p, _f64p, _intp, _f64p_or_null]
+    lib.oracle_traced_cgls.restype = None
+    lib.oracle_traced_free.argtypes = [ctypes.c_void_p]
+    lib.oracle_traced_free.restype = None
     for f in ("oracle_counts_A", "oracle_fill_A", "oracle_counts_AT", "oracle_fill_AT",
               "oracle_csr_spmm", "oracle_project_rows", "oracle_backproject_voxels", "oracle_cgls"):
         getattr(lib, f).restype = None
@@ -186,16 +200,74 @@ def backproject_voxels(N: int, M: int, C: int, y: np.ndarray, vox: np.ndarray) -
     return out
 
 
-def cgls(A: sp.csr_matrix, AT: sp.csr_matrix, y: np.ndarray, iters: int):
+def cgls(A: sp.csr_matrix, AT: sp.csr_matrix, y: np.ndarray, iters: int, history: bool = False):
     """Per-slice CGLS from x0 = 0.  y: (B, M*C).  Returns (x (B, N*N),
-    resid (iters+1, B) of ||r_k||/||y||, status (B,), 1 = stopped early)."""
+    resid (iters+1, B) of ||r_k||/||y||, status (B,), 1 = stopped early), and
+    with ``history`` also xhist (iters, B, N*N): x_k for k = 1..iters."""
     lib = _load()
     y = np.ascontiguousarray(y, dtype=np.float64).reshape(np.asarray(y).shape[0], -1)
     B = y.shape[0]
     x = np.empty((B, A.shape[1]), np.float64)
     resid = np.empty((iters + 1, B), np.float64)
     status = np.empty(B, np.int32)
+    xh = np.empty((iters, B, A.shape[1]), np.float64) if history else None
     ap, ac, av = _csr_parts(A)
     tp, tc, tv = _csr_parts(AT)
-    lib.oracle_cgls(A.shape[0], ap, ac, av, A.shape[1], tp, tc, tv, B, y, iters, x, resid, status)
-    return x, resid, status
+    lib.oracle_cgls(A.shape[0], ap, ac, av, A.shape[1], tp, tc, tv, B, y, iters, x, resid, status,
+                    xh.ctypes.data if history else None)
+    return (x, resid, status, xh) if history else (x, resid, status)
+
+
+class TracedA:
+    """The scan (N, M, C) with only A held in host memory, as a CSR traced ray
+    by ray inside the C library (12 bytes per entry); A^T is applied as A's
+    transposed product.  For scans where A and A^T would not both fit.  Use as
+    a context manager or call ``close``."""
+
+    def __init__(self, N: int, M: int, C: int):
+        self.N, self.M, self.C = N, M, C
+        self._h = _load().oracle_traced_build(N, M, C)
+        if not self._h:
+            raise MemoryError("oracle_traced_build: the CSR of A does not fit in host memory")
+
+    @property
+    def nnz(self) -> int:
+        return int(_load().oracle_traced_nnz(self._h))
+
+    def project(self, x: np.ndarray) -> np.ndarray:
+        """A x_b for x (B, N, N) or (B, N*N) -> (B, M*C)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(np.asarray(x).shape[0], -1)
+        assert x.shape[1] == self.N * self.N
+        y = np.empty((x.shape[0], self.M * self.C), np.float64)
+        _load().oracle_traced_project(self._h, x.shape[0], x, y)
+        return y
+
+    def cgls(self, y: np.ndarray, iters: int, history: bool = False):
+        """Per-slice CGLS as ``cgls``; same returns."""
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(np.asarray(y).shape[0], -1)
+        B = y.shape[0]
+        assert y.shape[1] == self.M * self.C
+        nc = self.N * self.N
+        x = np.empty((B, nc), np.float64)
+        resid = np.empty((iters + 1, B), np.float64)
+        status = np.empty(B, np.int32)
+        xh = np.empty((iters, B, nc), np.float64) if history else None
+        _load().oracle_traced_cgls(self._h, B, y, iters, x, resid, status, xh.ctypes.data if history else None)
+        return (x, resid, status, xh) if history else (x, resid, status)
+
+    def close(self):
+        if self._h:
+            _load().oracle_traced_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -35,8 +35,14 @@
  *                         line can meet the voxel, each clipped against the
  *                         voxel's two slabs (Liang-Barsky);
  *   brute.py           -- every (ray, voxel) pair by edge intersection.
+ *
+ * Products: CSR SpMV over rows of A and of the voxel-driven A^T; for scans
+ * too large to hold both, A alone (oracle_traced_*) with A^T w taken as the
+ * transposed product of A's rows.  CGLS runs on either form and can return
+ * every iterate.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -328,17 +334,72 @@ static double orc_dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
+/* The two products of CGLS for one slice: A v (nc -> nr) and A^T w
+ * (nr -> nc), through an explicit CSR of A and one of A^T, or through A's
+ * CSR alone (A^T w then taken as the transposed product, see below). */
+typedef struct {
+    int64_t nr, nc;
+    const int64_t *a_ptr;
+    const int32_t *a_col;
+    const double *a_val;
+    const int64_t *t_ptr; /* NULL: A^T w as the transposed product of A */
+    const int32_t *t_col;
+    const double *t_val;
+} orc_ops;
+
+/* x = A^T w from the rows of A: x[c] = sum over rows r of A[r][c] w[r].
+ * Each thread adds a fixed (static) range of rows into its own copy of x;
+ * the copies are then added in thread order. */
+static void orc_transposed_product(const orc_ops *o, const double *w, double *x)
+{
+    int nt = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        nt = omp_get_num_threads();
+    }
+    double *part = (double *)calloc((size_t)nt * (size_t)o->nc, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        double *xt = part + (size_t)omp_get_thread_num() * (size_t)o->nc;
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < o->nr; ++r)
+            for (int64_t n = o->a_ptr[r]; n < o->a_ptr[r + 1]; ++n) xt[o->a_col[n]] += o->a_val[n] * w[r];
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < o->nc; ++c) {
+        double v = 0.0;
+        for (int t = 0; t < nt; ++t) v += part[(size_t)t * (size_t)o->nc + c];
+        x[c] = v;
+    }
+    free(part);
+}
+
+static void orc_apply_A(const orc_ops *o, const double *v, double *out)
+{
+    oracle_csr_spmm(o->nr, o->a_ptr, o->a_col, o->a_val, o->nc, 1, v, out);
+}
+
+static void orc_apply_AT(const orc_ops *o, const double *w, double *out)
+{
+    if (o->t_ptr)
+        oracle_csr_spmm(o->nc, o->t_ptr, o->t_col, o->t_val, o->nr, 1, w, out);
+    else
+        orc_transposed_product(o, w, out);
+}
+
 /* CGLS (CG on A^T A x = A^T y) for each slice independently, from x = 0,
  * for exactly `iters` iterations: iters products with A and iters+1 with
- * A^T.  A is (nr x nc) in CSR; At is its transpose in CSR (nc x nr).
- * resid[k*batch + b] = ||y_b - A x_k|| / ||y_b|| for k = 0..iters (0 when
- * ||y_b|| = 0).  status[b] = 1 when the slice stopped early because a
- * step length or direction became zero (gamma = 0 or delta = 0), else 0;
- * a stopped slice keeps its iterate. */
-void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const double *a_val,
-                 int64_t nc, const int64_t *t_ptr, const int32_t *t_col, const double *t_val,
-                 int batch, const double *y, int iters, double *x, double *resid, int *status)
+ * A^T (Sec. IV-F; Table IV note).  resid[k*batch + b] = ||y_b - A x_k|| /
+ * ||y_b|| for k = 0..iters (0 when ||y_b|| = 0).  status[b] = 1 when the
+ * slice stopped early because a step length or direction became zero
+ * (gamma = 0 or delta = 0), else 0; a stopped slice keeps its iterate.
+ * xhist (nullable): xhist[((k-1)*batch + b)*nc ...] = x_k of slice b for
+ * k = 1..iters. */
+static void orc_cgls(const orc_ops *o, int batch, const double *y, int iters, double *x, double *resid, int *status,
+                     double *xhist)
 {
+    const int64_t nr = o->nr, nc = o->nc;
     double *r = (double *)malloc(sizeof(double) * (size_t)nr);
     double *q = (double *)malloc(sizeof(double) * (size_t)nr);
     double *s = (double *)malloc(sizeof(double) * (size_t)nc);
@@ -349,14 +410,14 @@ void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const d
         memset(xb, 0, sizeof(double) * (size_t)nc);
         memcpy(r, yb, sizeof(double) * (size_t)nr);
         double ynorm = sqrt(orc_dot(nr, yb, yb));
-        oracle_csr_spmm(nc, t_ptr, t_col, t_val, nr, 1, r, s);
+        orc_apply_AT(o, r, s);
         memcpy(p, s, sizeof(double) * (size_t)nc);
         double gamma = orc_dot(nc, s, s);
         int stopped = 0;
         resid[b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
         for (int k = 0; k < iters; ++k) {
             if (!stopped) {
-                oracle_csr_spmm(nr, a_ptr, a_col, a_val, nc, 1, p, q);
+                orc_apply_A(o, p, q);
                 double delta = orc_dot(nr, q, q);
                 if (gamma == 0.0 || delta == 0.0) {
                     stopped = 1;
@@ -364,7 +425,7 @@ void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const d
                     double alpha = gamma / delta;
                     for (int64_t n = 0; n < nc; ++n) xb[n] += alpha * p[n];
                     for (int64_t n = 0; n < nr; ++n) r[n] -= alpha * q[n];
-                    oracle_csr_spmm(nc, t_ptr, t_col, t_val, nr, 1, r, s);
+                    orc_apply_AT(o, r, s);
                     double gnew = orc_dot(nc, s, s);
                     double beta = gnew / gamma;
                     for (int64_t n = 0; n < nc; ++n) p[n] = s[n] + beta * p[n];
@@ -372,6 +433,7 @@ void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const d
                 }
             }
             resid[(int64_t)(k + 1) * batch + b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
+            if (xhist) memcpy(xhist + ((int64_t)k * batch + b) * nc, xb, sizeof(double) * (size_t)nc);
         }
         status[b] = stopped;
     }
@@ -379,4 +441,85 @@ void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const d
     free(q);
     free(s);
     free(p);
+}
+
+/* CGLS with an explicit CSR of A (nr x nc) and of its transpose At. */
+void oracle_cgls(int64_t nr, const int64_t *a_ptr, const int32_t *a_col, const double *a_val,
+                 int64_t nc, const int64_t *t_ptr, const int32_t *t_col, const double *t_val,
+                 int batch, const double *y, int iters, double *x, double *resid, int *status, double *xhist)
+{
+    orc_ops o = {nr, nc, a_ptr, a_col, a_val, t_ptr, t_col, t_val};
+    orc_cgls(&o, batch, y, iters, x, resid, status, xhist);
+}
+
+/* The scan (N, M, C) with only A stored: its CSR is traced ray by ray
+ * (Siddon, as oracle_fill_A) and A^T is applied as the transposed product,
+ * for scans whose A and A^T would not both fit in host memory (A alone takes
+ * 12 bytes per entry).  oracle_traced_build returns NULL when the matrix
+ * cannot be allocated. */
+typedef struct {
+    int N, M, C;
+    orc_ops o;
+} orc_traced;
+
+void *oracle_traced_build(int N, int M, int C)
+{
+    const int64_t R = (int64_t)M * C, V = (int64_t)N * N;
+    orc_traced *t = (orc_traced *)calloc(1, sizeof(orc_traced));
+    int64_t *ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+    if (!t || !ptr) {
+        free(t);
+        free(ptr);
+        return NULL;
+    }
+    oracle_counts_A(N, M, C, ptr + 1);
+    ptr[0] = 0;
+    for (int64_t r = 0; r < R; ++r) ptr[r + 1] += ptr[r];
+    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)ptr[R]);
+    double *vals = (double *)malloc(sizeof(double) * (size_t)ptr[R]);
+    if (!cols || !vals) {
+        free(t);
+        free(ptr);
+        free(cols);
+        free(vals);
+        return NULL;
+    }
+    oracle_fill_A(N, M, C, ptr, cols, vals);
+    t->N = N;
+    t->M = M;
+    t->C = C;
+    orc_ops o = {R, V, ptr, cols, vals, NULL, NULL, NULL};
+    t->o = o;
+    return t;
+}
+
+int64_t oracle_traced_nnz(const void *h)
+{
+    const orc_traced *t = (const orc_traced *)h;
+    return t->o.a_ptr[t->o.nr];
+}
+
+/* y_b = A x_b for `batch` slices (B x N^2 -> B x M C). */
+void oracle_traced_project(const void *h, int batch, const double *x, double *y)
+{
+    const orc_traced *t = (const orc_traced *)h;
+    oracle_csr_spmm(t->o.nr, t->o.a_ptr, t->o.a_col, t->o.a_val, t->o.nc, batch, x, y);
+}
+
+/* CGLS as oracle_cgls on the traced scan. */
+void oracle_traced_cgls(const void *h, int batch, const double *y, int iters, double *x, double *resid, int *status,
+                        double *xhist)
+{
+    const orc_traced *t = (const orc_traced *)h;
+    orc_cgls(&t->o, batch, y, iters, x, resid, status, xhist);
+}
+
+void oracle_traced_free(void *h)
+{
+    orc_traced *t = (orc_traced *)h;
+    if (!t) return;
+    free((void *)t->o.a_ptr);
+    free((void *)t->o.a_col);
+    free((void *)t->o.a_val);
+    free(t);
 }

@@ -235,6 +235,36 @@ def test_cgls_matches_krylov_least_squares(N, M, C):
             assert abs(res[k, b] - np.linalg.norm(r) / np.linalg.norm(y[b])) < 1e-9
 
 
+@pytest.mark.parametrize("N,M,C", [(8, 6, 8), (13, 10, 11)])
+def test_cgls_traced_and_history_match_krylov_least_squares(N, M, C):
+    """The matrix-free-build variant (A traced into CSR, A^T applied as A's
+    transposed product) and the per-iteration history reach the same
+    Krylov least-squares iterates as dense QR, and the history's x_k is the
+    iterate a k-iteration run returns."""
+    A = oracle.build_A(N, M, C)
+    AT = oracle.build_AT(N, M, C)
+    D = brute.dense_A(N, M, C)
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal((2, M * C))
+    K = 7
+    with oracle.TracedA(N, M, C) as T:
+        assert T.nnz == A.nnz
+        xr = rng.standard_normal((3, N * N))
+        np.testing.assert_array_equal(T.project(xr), oracle.spmm(A, xr))
+        xt, rest, stt, xht = T.cgls(y, K, history=True)
+    x, res, st, xh = oracle.cgls(A, AT, y, K, history=True)
+    assert xht.shape == (K, 2, N * N) and np.all(stt == 0)
+    for k in range(1, K + 1):
+        xk, _, _ = oracle.cgls(A, AT, y, k)
+        np.testing.assert_array_equal(xh[k - 1], xk)
+        for b in range(2):
+            ref = _krylov_ls(D, y[b], k)
+            assert np.linalg.norm(xht[k - 1, b] - ref) <= 1e-8 * np.linalg.norm(ref)
+            assert abs(rest[k, b] - np.linalg.norm(y[b] - D @ ref) / np.linalg.norm(y[b])) < 1e-9
+    np.testing.assert_array_equal(xht[-1], xt)
+    np.testing.assert_allclose(rest, res, rtol=1e-10, atol=1e-13)
+
+
 def test_cgls_reaches_min_norm_least_squares():
     N, M, C = 4, 6, 4
     A = oracle.build_A(N, M, C)
@@ -300,7 +330,7 @@ def test_cgls_iterates_amplify_rounding():
     rounding) leaves x_4 within 1e-5 of the exact iterate but moves x_10 by
     more than 1e-3 -- so FP32 or FP16 CGLS can match the FP64 iterates tightly
     only over the first iterations, and within the rounding envelope after."""
-    from cgls_envelope import envelope
+    from cgls_envelope import envelope_history
     from paper_2009_07226_amd import phantoms
     N, M, C = 128, 180, 128
     A = oracle.build_A(N, M, C)
@@ -308,10 +338,13 @@ def test_cgls_iterates_amplify_rounding():
     x_true = phantoms.ellipse_batch(N, 1, 10, seed=1)
     y = oracle.project(A, x_true.numpy().reshape(1, -1))
     y = y + 0.01 * y.max() * phantoms.noise((M * C,), [0], 1)
-    x4, _, _ = oracle.cgls(A, AT, y, 4)
-    x10, _, _ = oracle.cgls(A, AT, y, 10)
-    assert envelope(A, AT, y, x4, 4, 1e-7).max() < 1e-5
-    assert envelope(A, AT, y, x10, 10, 1e-7).max() > 1e-3
+    _, res, _, xh = oracle.cgls(A, AT, y, 10, history=True)
+    env_x, env_r = envelope_history(A, AT, y, xh, res, 10, 1e-7)
+    assert env_x[4].max() < 1e-5
+    assert env_x[10].max() > 1e-3
+    # the residual norm, which CGLS minimises over the Krylov space, is far
+    # less sensitive than the iterate while the iterate is still stable
+    assert env_r[1:7].max() < 1e-6
 
 
 # --- The generic gradient solver of Eq. (1) (oracle/gradient.py) ---
