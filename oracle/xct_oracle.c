@@ -347,100 +347,125 @@ typedef struct {
     const double *t_val;
 } orc_ops;
 
-/* x = A^T w from the rows of A: x[c] = sum over rows r of A[r][c] w[r].
- * Each thread adds a fixed (static) range of rows into its own copy of x;
- * the copies are then added in thread order. */
-static void orc_transposed_product(const orc_ops *o, const double *w, double *x)
+/* x_b = A^T w_b from the rows of A for `batch` slices: x_b[c] = sum over
+ * rows r of A[r][c] w_b[r].  Each thread adds a fixed (static) range of rows
+ * into its own copy of x; the copies are then added in thread order. */
+static void orc_transposed_product(const orc_ops *o, int batch, const double *w, double *x)
 {
+    const size_t nx = (size_t)batch * (size_t)o->nc;
     int nt = 1;
 #pragma omp parallel
     {
 #pragma omp single
         nt = omp_get_num_threads();
     }
-    double *part = (double *)calloc((size_t)nt * (size_t)o->nc, sizeof(double));
+    double *part = (double *)calloc((size_t)nt * nx, sizeof(double));
 #pragma omp parallel num_threads(nt)
     {
-        double *xt = part + (size_t)omp_get_thread_num() * (size_t)o->nc;
+        double *xt = part + (size_t)omp_get_thread_num() * nx;
 #pragma omp for schedule(static)
         for (int64_t r = 0; r < o->nr; ++r)
-            for (int64_t n = o->a_ptr[r]; n < o->a_ptr[r + 1]; ++n) xt[o->a_col[n]] += o->a_val[n] * w[r];
+            for (int b = 0; b < batch; ++b) {
+                const double wr = w[(int64_t)b * o->nr + r];
+                double *xb = xt + (size_t)b * (size_t)o->nc;
+                for (int64_t n = o->a_ptr[r]; n < o->a_ptr[r + 1]; ++n) xb[o->a_col[n]] += o->a_val[n] * wr;
+            }
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < o->nc; ++c) {
+    for (int64_t c = 0; c < (int64_t)nx; ++c) {
         double v = 0.0;
-        for (int t = 0; t < nt; ++t) v += part[(size_t)t * (size_t)o->nc + c];
+        for (int t = 0; t < nt; ++t) v += part[(size_t)t * nx + (size_t)c];
         x[c] = v;
     }
     free(part);
 }
 
-static void orc_apply_A(const orc_ops *o, const double *v, double *out)
+/* out_b = A v_b for `batch` slices */
+static void orc_apply_A(const orc_ops *o, int batch, const double *v, double *out)
 {
-    oracle_csr_spmm(o->nr, o->a_ptr, o->a_col, o->a_val, o->nc, 1, v, out);
+    oracle_csr_spmm(o->nr, o->a_ptr, o->a_col, o->a_val, o->nc, batch, v, out);
 }
 
-static void orc_apply_AT(const orc_ops *o, const double *w, double *out)
+/* out_b = A^T w_b for `batch` slices */
+static void orc_apply_AT(const orc_ops *o, int batch, const double *w, double *out)
 {
     if (o->t_ptr)
-        oracle_csr_spmm(o->nc, o->t_ptr, o->t_col, o->t_val, o->nr, 1, w, out);
+        oracle_csr_spmm(o->nc, o->t_ptr, o->t_col, o->t_val, o->nr, batch, w, out);
     else
-        orc_transposed_product(o, w, out);
+        orc_transposed_product(o, batch, w, out);
 }
 
 /* CGLS (CG on A^T A x = A^T y) for each slice independently, from x = 0,
  * for exactly `iters` iterations: iters products with A and iters+1 with
- * A^T (Sec. IV-F; Table IV note).  resid[k*batch + b] = ||y_b - A x_k|| /
- * ||y_b|| for k = 0..iters (0 when ||y_b|| = 0).  status[b] = 1 when the
- * slice stopped early because a step length or direction became zero
- * (gamma = 0 or delta = 0), else 0; a stopped slice keeps its iterate.
- * xhist (nullable): xhist[((k-1)*batch + b)*nc ...] = x_k of slice b for
- * k = 1..iters. */
+ * A^T (Sec. IV-F; Table IV note).  The slices share each product (one pass
+ * over the matrix for all of them) but nothing else: every slice has its own
+ * alpha, beta, gamma and delta, and its sums are the same as in a run on that
+ * slice alone.  resid[k*batch + b] = ||y_b - A x_k|| / ||y_b|| for
+ * k = 0..iters (0 when ||y_b|| = 0).  status[b] = 1 when the slice stopped
+ * early because a step length or direction became zero (gamma = 0 or
+ * delta = 0), else 0; a stopped slice keeps its iterate.  xhist (nullable):
+ * xhist[((k-1)*batch + b)*nc ...] = x_k of slice b for k = 1..iters. */
 static void orc_cgls(const orc_ops *o, int batch, const double *y, int iters, double *x, double *resid, int *status,
                      double *xhist)
 {
     const int64_t nr = o->nr, nc = o->nc;
-    double *r = (double *)malloc(sizeof(double) * (size_t)nr);
-    double *q = (double *)malloc(sizeof(double) * (size_t)nr);
-    double *s = (double *)malloc(sizeof(double) * (size_t)nc);
-    double *p = (double *)malloc(sizeof(double) * (size_t)nc);
+    const size_t B = (size_t)batch;
+    double *r = (double *)malloc(sizeof(double) * B * (size_t)nr);
+    double *q = (double *)malloc(sizeof(double) * B * (size_t)nr);
+    double *s = (double *)malloc(sizeof(double) * B * (size_t)nc);
+    double *p = (double *)malloc(sizeof(double) * B * (size_t)nc);
+    double *gamma = (double *)malloc(sizeof(double) * B);
+    double *ynorm = (double *)malloc(sizeof(double) * B);
+    int *stepped = (int *)malloc(sizeof(int) * B);
+    memset(x, 0, sizeof(double) * B * (size_t)nc);
+    memcpy(r, y, sizeof(double) * B * (size_t)nr);
+    orc_apply_AT(o, batch, r, s);
+    memcpy(p, s, sizeof(double) * B * (size_t)nc);
     for (int b = 0; b < batch; ++b) {
         const double *yb = y + (int64_t)b * nr;
-        double *xb = x + (int64_t)b * nc;
-        memset(xb, 0, sizeof(double) * (size_t)nc);
-        memcpy(r, yb, sizeof(double) * (size_t)nr);
-        double ynorm = sqrt(orc_dot(nr, yb, yb));
-        orc_apply_AT(o, r, s);
-        memcpy(p, s, sizeof(double) * (size_t)nc);
-        double gamma = orc_dot(nc, s, s);
-        int stopped = 0;
-        resid[b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
-        for (int k = 0; k < iters; ++k) {
-            if (!stopped) {
-                orc_apply_A(o, p, q);
-                double delta = orc_dot(nr, q, q);
-                if (gamma == 0.0 || delta == 0.0) {
-                    stopped = 1;
-                } else {
-                    double alpha = gamma / delta;
-                    for (int64_t n = 0; n < nc; ++n) xb[n] += alpha * p[n];
-                    for (int64_t n = 0; n < nr; ++n) r[n] -= alpha * q[n];
-                    orc_apply_AT(o, r, s);
-                    double gnew = orc_dot(nc, s, s);
-                    double beta = gnew / gamma;
-                    for (int64_t n = 0; n < nc; ++n) p[n] = s[n] + beta * p[n];
-                    gamma = gnew;
-                }
+        ynorm[b] = sqrt(orc_dot(nr, yb, yb));
+        gamma[b] = orc_dot(nc, s + (int64_t)b * nc, s + (int64_t)b * nc);
+        status[b] = 0;
+        resid[b] = ynorm[b] > 0.0 ? sqrt(orc_dot(nr, yb, yb)) / ynorm[b] : 0.0;
+    }
+    for (int k = 0; k < iters; ++k) {
+        orc_apply_A(o, batch, p, q);
+        for (int b = 0; b < batch; ++b) {
+            double *xb = x + (int64_t)b * nc, *pb = p + (int64_t)b * nc;
+            double *rb = r + (int64_t)b * nr, *qb = q + (int64_t)b * nr;
+            stepped[b] = 0;
+            if (status[b]) continue;
+            const double delta = orc_dot(nr, qb, qb);
+            if (gamma[b] == 0.0 || delta == 0.0) {
+                status[b] = 1;
+                continue;
             }
-            resid[(int64_t)(k + 1) * batch + b] = ynorm > 0.0 ? sqrt(orc_dot(nr, r, r)) / ynorm : 0.0;
-            if (xhist) memcpy(xhist + ((int64_t)k * batch + b) * nc, xb, sizeof(double) * (size_t)nc);
+            const double alpha = gamma[b] / delta;
+            for (int64_t n = 0; n < nc; ++n) xb[n] += alpha * pb[n];
+            for (int64_t n = 0; n < nr; ++n) rb[n] -= alpha * qb[n];
+            stepped[b] = 1;
         }
-        status[b] = stopped;
+        orc_apply_AT(o, batch, r, s);
+        for (int b = 0; b < batch; ++b) {
+            double *pb = p + (int64_t)b * nc, *sb = s + (int64_t)b * nc, *rb = r + (int64_t)b * nr;
+            if (stepped[b]) {
+                const double gnew = orc_dot(nc, sb, sb);
+                const double beta = gnew / gamma[b];
+                for (int64_t n = 0; n < nc; ++n) pb[n] = sb[n] + beta * pb[n];
+                gamma[b] = gnew;
+            }
+            resid[(int64_t)(k + 1) * batch + b] = ynorm[b] > 0.0 ? sqrt(orc_dot(nr, rb, rb)) / ynorm[b] : 0.0;
+            if (xhist)
+                memcpy(xhist + ((int64_t)k * batch + b) * nc, x + (int64_t)b * nc, sizeof(double) * (size_t)nc);
+        }
     }
     free(r);
     free(q);
     free(s);
     free(p);
+    free(gamma);
+    free(ynorm);
+    free(stepped);
 }
 
 /* CGLS with an explicit CSR of A (nr x nc) and of its transpose At. */
