@@ -81,6 +81,8 @@ def _load():
     lib.oracle_traced_nnz.restype = L
     lib.oracle_traced_project.argtypes = [ctypes.c_void_p, I, _f64p, _f64p]
     lib.oracle_traced_project.restype = None
+    lib.oracle_traced_backproject.argtypes = [ctypes.c_void_p, I, _f64p, _f64p]
+    lib.oracle_traced_backproject.restype = None
     lib.oracle_traced_cgls.argtypes = [ctypes.c_void_p, I, _f64p, I, _f64p, _f64p, _intp, _f64p_or_null]
     lib.oracle_traced_cgls.restype = None
     lib.oracle_traced_free.argtypes = [ctypes.c_void_p]
@@ -241,6 +243,15 @@ class TracedA:
         y = np.empty((x.shape[0], self.M * self.C), np.float64)
         _load().oracle_traced_project(self._h, x.shape[0], x, y)
         return y
+
+    def backproject(self, w: np.ndarray) -> np.ndarray:
+        """A^T w_b (the transposed product of A's rows) for w (B, M, C) or
+        (B, M*C) -> (B, N*N)."""
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(np.asarray(w).shape[0], -1)
+        assert w.shape[1] == self.M * self.C
+        x = np.empty((w.shape[0], self.N * self.N), np.float64)
+        _load().oracle_traced_backproject(self._h, w.shape[0], w, x)
+        return x
 
     def cgls(self, y: np.ndarray, iters: int, history: bool = False):
         """Per-slice CGLS as ``cgls``; same returns."""

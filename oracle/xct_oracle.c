@@ -531,6 +531,14 @@ void oracle_traced_project(const void *h, int batch, const double *x, double *y)
     oracle_csr_spmm(t->o.nr, t->o.a_ptr, t->o.a_col, t->o.a_val, t->o.nc, batch, x, y);
 }
 
+/* x_b = A^T w_b for `batch` slices (B x M C -> B x N^2), as the transposed
+ * product of A's rows. */
+void oracle_traced_backproject(const void *h, int batch, const double *w, double *x)
+{
+    const orc_traced *t = (const orc_traced *)h;
+    orc_transposed_product(&t->o, batch, w, x);
+}
+
 /* CGLS as oracle_cgls on the traced scan. */
 void oracle_traced_cgls(const void *h, int batch, const double *y, int iters, double *x, double *resid, int *status,
                         double *xhist)

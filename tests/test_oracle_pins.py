@@ -251,6 +251,10 @@ def test_cgls_traced_and_history_match_krylov_least_squares(N, M, C):
         assert T.nnz == A.nnz
         xr = rng.standard_normal((3, N * N))
         np.testing.assert_array_equal(T.project(xr), oracle.spmm(A, xr))
+        # the transposed product of the traced rows against the independent
+        # voxel-driven A^T
+        wr = rng.standard_normal((3, M * C))
+        np.testing.assert_allclose(T.backproject(wr), oracle.spmm(AT, wr), rtol=1e-12, atol=1e-12)
         xt, rest, stt, xht = T.cgls(y, K, history=True)
     x, res, st, xh = oracle.cgls(A, AT, y, K, history=True)
     assert xht.shape == (K, 2, N * N) and np.all(stt == 0)
@@ -339,7 +343,7 @@ def test_cgls_iterates_amplify_rounding():
     y = oracle.project(A, x_true.numpy().reshape(1, -1))
     y = y + 0.01 * y.max() * phantoms.noise((M * C,), [0], 1)
     _, res, _, xh = oracle.cgls(A, AT, y, 10, history=True)
-    env_x, env_r = envelope_history(A, AT, y, xh, res, 10, 1e-7)
+    env_x, env_r = envelope_history(A, AT, y, xh, res, 10, storage="f64", eps=1e-7)
     assert env_x[4].max() < 1e-5
     assert env_x[10].max() > 1e-3
     # the residual norm, which CGLS minimises over the Krylov space, is far
