@@ -9,6 +9,9 @@ Workloads (seeded synthetic stand-ins for the paper's datasets):
   8 slices 512^2, 360 angles (differentiable form, Adam + TV);
   128 slices 2816^2, 2250 angles, 2816 channels, FP16 matrix (large share).
 """
+import os
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -21,8 +24,20 @@ pytestmark = pytest.mark.gpu
 xct = pytest.importorskip("paper_2009_07226_amd")
 
 
+_PROGRESS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
+                         "fullsize_progress.log")
+
+
 def banner(msg):
+    """Print a progress line, and append it to a log file (the long tests'
+    steps take minutes each while pytest holds their printed output)."""
     print(f"[gpu-test] {msg}", flush=True)
+    try:
+        os.makedirs(os.path.dirname(_PROGRESS), exist_ok=True)
+        with open(_PROGRESS, "a") as f:
+            f.write(f"{time.strftime('%H:%M:%S')} {msg}\n")
+    except OSError:
+        pass
 
 
 def sampled_rel_err(got, ref):
@@ -78,6 +93,40 @@ def test_bench_workload_16x1024_1500():
     cgls_properties(A, yn, 30, x)
 
 
+def test_fp16_matrix_decodes_at_16x1024_1500():
+    """The whole FP16 operator pair at 1024^2, 1500 angles decodes: every
+    stored step is either padding or an entry whose FP16 length is non-zero
+    (lengths that round to zero are not entries), the count equals nnz, and
+    sampled rays and voxels carry the oracle's lengths rounded to FP16."""
+    N, M, C = 1024, 1500, 1024
+    A = xct.Matrix(N, M, C, "f16")
+    info = A.info()
+    rng = np.random.default_rng(21)
+    for which in (0, 1):
+        r, c, v = A.to_coo(which)
+        assert r.size == info["AT" if which else "A"]["nnz"]
+        assert np.all(v > 0)
+        picks = rng.choice(M * C if which == 0 else N * N, 48, replace=False)
+        sel = np.isin(r, picks)
+        rs, cs, vs = r[sel], c[sel], v[sel]
+        for q in picks:
+            if which == 0:
+                oc, ov = oracle.siddon_row(N, M, C, int(q))
+            else:
+                oc, ov = oracle.voxel_col(N, M, C, int(q))
+            o16 = ov.astype(np.float16).astype(np.float32)
+            keep = o16 != 0
+            m = rs == q
+            order = np.argsort(cs[m])
+            oo = np.argsort(oc[keep])
+            np.testing.assert_array_equal(cs[m][order], oc[keep][oo])
+            ulp = np.spacing(o16[keep][oo].astype(np.float16)).astype(np.float32)
+            assert np.all(np.abs(vs[m][order] - o16[keep][oo]) <= ulp)
+        banner(f"FP16 {'A^T' if which else 'A'} decoded: {r.size} entries")
+        del r, c, v
+    A.free()
+
+
 @pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f16", 2e-3)])
 def test_workload_64x2048_1500(dt, tol):
     N, M, C, B = 2048, 1500, 2048, 64
@@ -110,6 +159,69 @@ def test_workload_64x2048_fp16_cgls_tracks_fp32():
     assert float((e16 - e32).abs().max()) < 0.05
     del A16
     torch.cuda.empty_cache()
+
+
+def test_workload_64x2048_cgls_every_iteration_vs_oracle():
+    """FP32, FP16 and BF16 CGLS at 2048^2, 1500 angles, 2048 channels against
+    the FP64 oracle at every one of the first 3 iterations, on 2 slices of the
+    60-ellipsoid phantom with 1% noise (slices are independent, so 2 slices
+    stand for the 64-slice batch; the sinogram is the GPU's FP32 projection
+    plus noise, shared by both sides).  The oracle holds only A (90 GB as a
+    CSR in host memory) and applies A^T as its transposed product.
+
+    Over the first 3 iterations rounding is not yet amplified (the envelope
+    studies at 128^2 and 512^2 grow by less than 2x by k = 3), so each format
+    is held to its single-product bar at every k, for the iterate and the
+    residual norm: FP32 1e-5, FP16 the 1e-3 gate, BF16 8e-3 (the FP16 gate
+    times the ratio 2^3 of the two formats' unit roundoffs)."""
+    N, M, C, iters = 2048, 1500, 2048, 3
+    sl = [17, 40]
+    B = len(sl)
+    bars = {"f32": 1e-5, "f16": 1e-3, "bf16": 8e-3}
+    x4 = phantoms.ellipsoid_phantom(N, 64, 60, seed=4, device="cuda").float()
+    gpu = {}
+    y = None
+    for dt in ("f32", "f16", "bf16"):
+        torch.cuda.empty_cache()
+        A = xct.Matrix(N, M, C, dt)
+        if y is None:
+            y = xct.project(A, x4[sl].contiguous())
+            y = (y + 0.01 * float(y.abs().max()) * phantoms.noise_torch((M, C), B, 4, "cuda")).contiguous()
+            del x4
+        gpu[dt] = gpu_iterates(A, y, iters)
+        A.free()
+        del A
+        banner(f"64x2048 per-iteration: GPU CGLS {dt} done")
+    torch.cuda.empty_cache()
+    yd = y.double().cpu().numpy().reshape(B, -1)
+    with oracle.TracedA(N, M, C) as T:
+        banner(f"  oracle A traced: nnz {T.nnz}")
+        xo, reso, sto, xho = T.cgls(yd, iters, history=True)
+    banner("  oracle CGLS done")
+    for dt in ("f32", "f16", "bf16"):
+        xg, resg, stg = gpu[dt]
+        assert np.all(stg == sto)
+        for k in range(1, iters + 1):
+            ex = rel_err_rows(xg[k - 1], xho[k - 1])
+            er = np.abs(resg[k] - reso[k]) / reso[k]
+            banner(f"  2048 {dt} k={k}: x rel err {ex.max():.2e}, residual rel dev {er.max():.2e} "
+                   f"(bar {bars[dt]:g})")
+            assert ex.max() <= bars[dt] and er.max() <= bars[dt], (dt, k, ex, er)
+
+
+def gpu_iterates(A, y, iters):
+    """x_1..x_iters of the GPU CGLS as (iters, B, cols) FP64 (one run per k:
+    the solver is deterministic), with the last run's residuals and status."""
+    B = y.shape[0]
+    xs = []
+    for k in range(1, iters + 1):
+        x, res, st = xct.cgls(A, y, k)
+        xs.append(x.double().cpu().numpy().reshape(B, -1))
+    return np.stack(xs), res, st
+
+
+def rel_err_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
 def tv(x, eps=1e-2):
