@@ -1,9 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of the XCT hot path on one MI355X.
 
-Workload (the paper-shaped batch the headline metric is quoted on): 16 slices
-of 1024 x 1024 voxels, 1500 angles over [0, pi), 1024 channels, one shared
-Siddon matrix; seeded 40-ellipsoid phantom, synthetic data.
+Headline workload (the paper-shaped batch the headline metric is quoted on):
+16 slices of 1024 x 1024 voxels, 1500 angles over [0, pi), 1024 channels, one
+shared Siddon matrix; seeded 40-ellipsoid phantom, synthetic data.
 
 A step is one forward projection y = A x plus one backprojection x = A^T y
 of the whole 16-slice batch through the C ABI (FP32 path: matrix values FP32
@@ -15,16 +15,26 @@ The roofline object covers the SpMM kernel (both operators are launches of
 the same kernel): its algorithmic bytes per launch divided by its launch
 durations, measured with HIP events on the launch stream.
 
-Also reported: CGLS seconds per iteration for the FP32 matrix and for the
-FP16 matrix (16-bit storage of matrix values and kernel operands, FP32
-accumulation), and the FP64 CPU oracle timed on a bounded sample of the same
-products on the host cores.
+Also reported (each in its own object of the JSON line):
+  * CGLS seconds per iteration for the FP32 matrix and for the FP16 matrix
+    (16-bit storage of matrix values and kernel operands, FP32 accumulation);
+  * the 64 x 2048^2 x 1500 batch (FP32, FP16, BF16: kernel share of the HBM
+    peak, step and CGLS s/iter) and the 128 x 2816^2 x 2250 share (FP16:
+    kernel share, 20 CGLS iterations);
+  * the CPU oracle leg: the FP64 oracle timed on a bounded sample of the
+    headline products on the host cores (all cores and one core, median of
+    three), and the relative errors of the GPU outputs against the oracle:
+    sampled rays and voxels of the headline products, CGLS per iteration
+    (FP32, FP16, BF16) on 2 slices of 512^2 x 360 over 30 iterations and on 2
+    slices of 2048^2 x 1500 over the first 3 iterations.
 """
 import argparse
 import json
 import math
 import os
+import subprocess
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +43,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "fwd+back projection GB/s & % HBM peak; CGLS s/iter, FP16-store vs FP32"
+BYTES_A = {"f32": 6, "f16": 4, "bf16": 4}    # stored bytes per matrix entry
+BYTES_X = {"f32": 4, "f16": 2, "bf16": 2}    # staged operand bytes per element
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def alg_bytes(nnz, n_in, n_out, B, F, b_a, b_vec=4):
@@ -56,44 +72,237 @@ def measured_traffic(dtype, N, M, B, default_opts):
     return tot / n if n else None
 
 
-def cpu_baseline(N, M, C, B, x_host, bytes_step, budget_s):
-    """FP64 oracle (matrix-free sampled rows of A and voxels of A^T) on the host cores."""
+# ---- GPU measurements -----------------------------------------------------------
+
+def time_products(xct, torch, A, x, steps, warmup=2):
+    """Projection + backprojection of the batch x, `steps` times: ms per step
+    and, from the library's launch events, the SpMM kernel's launch times and
+    its algorithmic byte rate (matrix entries + staged operand in + FP32 out)."""
+    info = A.info()
+    dt = {0: "f32", 1: "f16", 2: "bf16"}[info["value_dtype"]]
+    B, N, M, C = x.shape[0], A.n, A.n_angles, A.n_channels
+    F = min(int(info["fuse"]), 1 << max(0, (B - 1).bit_length()))
+    y = torch.empty((B, M, C), dtype=x.dtype, device=x.device)
+    xb = torch.empty_like(x)
+    ws = A.spmm_workspace(B)
+    for _ in range(warmup):
+        xct.project(A, x, out=y, workspace=ws)
+        xct.backproject(A, y, out=xb, workspace=ws)
+    torch.cuda.synchronize()
+    xct.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        xct.project(A, x, out=y, workspace=ws)
+        xct.backproject(A, y, out=xb, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    xct.profile_enable(False)
+    prof = xct.profile_read()
+    ms = e0.elapsed_time(e1) / steps
+    b_a, b_x = BYTES_A[dt], BYTES_X[dt]
+    nnzA, nnzT = info["A"]["nnz"], info["AT"]["nnz"]
+    kb = {"A": nnzA * b_a + F * (N * N * b_x + M * C * 4), "AT": nnzT * b_a + F * (M * C * b_x + N * N * 4)}
+    (nA, msA), (nT, msT) = prof["A"], prof["AT"]
+    ach = (kb["A"] * nA + kb["AT"] * nT) / ((msA + msT) * 1e-3) / 1e9
+    step_bytes = alg_bytes(nnzA, N * N, M * C, B, F, b_a) + alg_bytes(nnzT, M * C, N * N, B, F, b_a)
+    del y, xb, ws
+    return {"dtype": dt, "fuse": F, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall / steps * 1e3, 4),
+            "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 2), "bytes_step": step_bytes,
+            "kernel_GBps": round(ach, 2), "kernel_frac": round(ach / HBM_PEAK_GBS, 4),
+            "avg_launch_ms": round((msA + msT) / max(nA + nT, 1), 4),
+            "launch_ms": {"A": round(msA / max(nA, 1), 4), "AT": round(msT / max(nT, 1), 4)},
+            "alg_bytes_per_launch": kb, "nnz": nnzA, "padded_A": info["A"]["padded"],
+            "padded_AT": info["AT"]["padded"], "build_s": round(info["build_seconds"], 3)}
+
+
+def cgls_seconds(xct, torch, A, y, iters, reps=2):
+    """Best of `reps` timed CGLS runs of `iters` iterations (no residual copy)."""
+    B = y.shape[0]
+    wsc = A.cgls_workspace(B, iters)
+    xo = torch.empty((B, A.n, A.n), dtype=torch.float32, device=y.device)
+    xct.cgls(A, y, iters, out=xo, workspace=wsc, want_resid=False)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        xct.cgls(A, y, iters, out=xo, workspace=wsc, want_resid=False)
+        s1.record()
+        torch.cuda.synchronize()
+        best = min(best, s0.elapsed_time(s1) * 1e-3)
+    return best
+
+
+def cgls_s_per_iter(xct, torch, A, y, iters):
+    """(t(iters) - t(0)) / iters: the setup backprojection excluded."""
+    return (cgls_seconds(xct, torch, A, y, iters) - cgls_seconds(xct, torch, A, y, 0)) / iters
+
+
+def gpu_cgls_iterates(xct, A, y, K):
+    """x_1..x_K of the GPU CGLS as a host FP64 array (K, B, cols), one run per
+    k (the solver is deterministic), and the K-run's residual history."""
     import numpy as np
+    xs = []
+    res = None
+    for k in range(1, K + 1):
+        x, res, _ = xct.cgls(A, y, k)
+        xs.append(x.double().cpu().numpy().reshape(y.shape[0], -1))
+    return np.stack(xs), res
 
-    import oracle
 
+# ---- the CPU oracle leg (the FP64 oracle: timing and errors) ---------------------
+
+def rel_l2_rows(a, b):
+    import numpy as np
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def per_iteration_errors(xg, xo):
+    """max over slices of ||x_k - x_k*|| / ||x_k*||, k = 1..K"""
+    return [float(rel_l2_rows(xg[k], xo[k]).max()) for k in range(xg.shape[0])]
+
+
+def holds_through(errs, bar):
+    """last k such that every iterate up to k is within `bar` (0: not even x_1)"""
+    k = 0
+    for e in errs:
+        if e > bar:
+            break
+        k += 1
+    return k
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+def cpu_baseline(oracle, N, M, C, B, x_host, ys, bytes_step, budget_s, threads):
+    """The FP64 oracle (matrix-free: sampled rows of A and voxels of A^T over
+    all B slices) on the host cores: a calibration, then three samples sized
+    to about budget_s / 4 each at all cores (median reported) and one at a
+    single core; full-step time extrapolated linearly in rows and voxels."""
+    import numpy as np
     rng = np.random.default_rng(0)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    oracle.set_threads(threads)
-    ys = rng.random((B, M * C))
 
-    def rate(fn, total, n0):
-        idx = rng.choice(total, n0, replace=False)
+    def rates(n_rows, n_vox):
+        ir = rng.choice(M * C, n_rows, replace=False)
+        iv = rng.choice(N * N, n_vox, replace=False)
         t = time.perf_counter()
-        fn(idx)
-        return n0 / (time.perf_counter() - t)
+        oracle.project_rows(N, M, C, x_host, ir)
+        tr = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.backproject_voxels(N, M, C, ys, iv)
+        tv = time.perf_counter() - t
+        return n_rows / tr, n_vox / tv
 
-    fr = lambda idx: oracle.project_rows(N, M, C, x_host, idx)
-    fb = lambda idx: oracle.backproject_voxels(N, M, C, ys, idx)
-    # calibrate, then time a sample sized to about budget_s of CPU work
-    r_rows = rate(fr, M * C, 256)
-    r_vox = rate(fb, N * N, 256)
-    n_rows = int(min(M * C, max(512, r_rows * budget_s / 2)))
-    n_vox = int(min(N * N, max(512, r_vox * budget_s / 2)))
-    r_rows = rate(fr, M * C, n_rows)
-    r_vox = rate(fb, N * N, n_vox)
-    t_full = M * C / r_rows + N * N / r_vox
+    oracle.set_threads(threads)
+    r_rows, r_vox = rates(256, 256)  # calibration (also the warm-up)
+    per = budget_s / 4.0
+    n_rows = int(min(M * C, max(512, r_rows * per / 2)))
+    n_vox = int(min(N * N, max(512, r_vox * per / 2)))
+    t_full = []
+    for _ in range(3):
+        rr, rv = rates(n_rows, n_vox)
+        t_full.append(M * C / rr + N * N / rv)
+    t_med = float(np.median(t_full))
+    oracle.set_threads(1)
+    n1r, n1v = max(64, n_rows // threads), max(64, n_vox // threads)
+    rr, rv = rates(n1r, n1v)
+    t_one = M * C / rr + N * N / rv
+    oracle.set_threads(threads)
     return {
-        "value": bytes_step / t_full / 1e9,
+        "value": bytes_step / t_med / 1e9,
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": (f"FP64 oracle, matrix-free: {n_rows} random rays of A and {n_vox} random voxels of A^T, "
-                   f"each over all {B} slices; full-step time extrapolated linearly "
-                   f"({t_full:.1f} s per fwd+back step)"),
-        "s_per_step": t_full,
+                   f"each over all {B} slices, on {threads} threads, median of 3 after a calibration run; "
+                   f"full-step time extrapolated linearly ({t_med:.1f} s per fwd+back step); one core: "
+                   f"{n1r} rays and {n1v} voxels"),
+        "s_per_step": t_med,
+        "s_per_step_runs": [round(t, 3) for t in t_full],
+        "one_core": {"value": bytes_step / t_one / 1e9, "unit": "GB/s", "s_per_step": t_one},
     }
 
+
+def headline_errors(oracle, xct, torch, A, N, M, C, x, y, slices, seed=7, n=512):
+    """Relative L2 (max over the listed slices) of the headline products on
+    sampled outputs: rays of A x and voxels of A^T y (y the GPU projection)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(M * C, n, replace=False)
+    vox = rng.choice(N * N, n, replace=False)
+    xs = x[slices].double().cpu().numpy().reshape(len(slices), -1)
+    ref = oracle.project_rows(N, M, C, xs, rows)
+    got = y[slices].reshape(len(slices), -1)[:, torch.from_numpy(rows).to(y.device)].double().cpu().numpy()
+    e_p = float(rel_l2_rows(got, ref).max())
+    xb = xct.backproject(A, y)
+    ref = oracle.backproject_voxels(N, M, C, y[slices].double().cpu().numpy(), vox)
+    got = xb[slices].reshape(len(slices), -1)[:, torch.from_numpy(vox).to(y.device)].double().cpu().numpy()
+    e_b = float(rel_l2_rows(got, ref).max())
+    return {"projection_rel_l2": e_p, "backprojection_rel_l2": e_b, "slices": list(slices),
+            "samples": f"{n} random rays of A x and {n} random voxels of A^T (A x), traced by the oracle"}
+
+
+def cgls_errors_512(oracle, xct, torch, phantoms, dev, iters=30):
+    """CGLS iterates of the three storage formats against the oracle's, every
+    iteration, on 2 slices of 512^2 x 360 (1% noise)."""
+    N, M, C = 512, 360, 512
+    Ao, ATo = oracle.build_A(N, M, C), oracle.build_AT(N, M, C)
+    x_true = phantoms.ellipsoid_phantom(N, 8, 20, seed=3)[[2, 5]]
+    y = oracle.project(Ao, x_true.numpy().reshape(2, -1))
+    y = y + 0.01 * y.max() * phantoms.noise((M * C,), [2, 5], 3)
+    y32 = torch.from_numpy(y).float().reshape(2, M, C)
+    _, reso, _, xho = oracle.cgls(Ao, ATo, y32.double().numpy().reshape(2, -1), iters, history=True)
+    out = {"workload": "2 slices 512x512, 360 angles, 512 channels, 20-ellipsoid phantom, 1% noise",
+           "k": list(range(1, iters + 1))}
+    for dt in ("f32", "f16", "bf16"):
+        A = xct.Matrix(N, M, C, dt)
+        xg, resg = gpu_cgls_iterates(xct, A, y32.to(dev), iters)
+        out[dt] = [round(e, 8) for e in per_iteration_errors(xg, xho)]
+        out[dt + "_residual_rel_dev_max"] = float((abs(resg - reso) / reso).max())
+        A.free()
+    out["f32_within_1e-4_through_k"] = holds_through(out["f32"], 1e-4)
+    out["f16_within_1e-3_through_k"] = holds_through(out["f16"], 1e-3)
+    out["bf16_within_1e-3_through_k"] = holds_through(out["bf16"], 1e-3)
+    return out
+
+
+class TracedOracleCgls(threading.Thread):
+    """The oracle's CGLS history on a few slices of a scan too large for an
+    explicit A and A^T in host memory (A traced into a CSR, A^T applied as its
+    transposed product), run on the host while the GPU measurements go on."""
+
+    def __init__(self, oracle, N, M, C, y, iters, threads):
+        super().__init__(daemon=True)
+        self.args = (oracle, N, M, C, y, iters, threads)
+        self.result, self.error, self.seconds = None, None, None
+
+    def run(self):
+        oracle, N, M, C, y, iters, threads = self.args
+        t = time.perf_counter()
+        try:
+            oracle.set_threads(threads)
+            with oracle.TracedA(N, M, C) as T:
+                _, res, _, xh = T.cgls(y, iters, history=True)
+            self.result = (xh, res)
+        except Exception as e:  # reported in the JSON line, never raised from the thread
+            self.error = repr(e)
+        self.seconds = time.perf_counter() - t
+
+
+# ---- main ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -102,8 +311,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cgls-iters", type=int, default=30)
     ap.add_argument("--no-cgls", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (timing and errors)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 64 x 2048^2 and 128 x 2816^2 workloads")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--angles", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=16)
@@ -112,7 +322,8 @@ def main():
     ap.add_argument("--tile-waves", type=int, default=0)
     ap.add_argument("--lane-order", type=int, default=0)
     ap.add_argument("--slab-order", type=int, default=0)
-    ap.add_argument("--fuse", type=int, default=0, help="slices fused per matrix pass (1, 2, 4, 8, 16; default 16)")
+    ap.add_argument("--fuse", type=int, default=0,
+                    help="slices fused per matrix pass (1, 2, 4, 8, 16, or 32 for 16-bit matrices; default 16)")
     ap.add_argument("--arith", type=int, default=0,
                     help="1: FP16 arithmetic for the FP16 matrices (the paper's half-precision variant)")
     ap.add_argument("--streamed", type=int, default=0, metavar="BATCH",
@@ -137,37 +348,27 @@ def main():
     from paper_2009_07226_amd import gradient as pgrad
     from paper_2009_07226_amd import phantoms
 
+    oracle = None
+    if not args.no_cpu:
+        import oracle  # the CPU oracle leg only: timing and error reports
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))  # the host's oracle threads
+
     N, M, C, B = args.n, args.angles, args.n, args.batch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    default_opts = not (args.stage_order or args.lds_bytes or args.tile_waves or args.fuse or args.arith or
+                        args.lane_order or args.slab_order)
 
     log(f"building {args.dtype} matrix N={N} M={M} C={C}")
     opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves, fuse=args.fuse,
                 lane_order=args.lane_order, slab_order=args.slab_order)
     opts16 = dict(opts, arith=args.arith)  # FP16 arithmetic applies to FP16 matrices only
     A = xct.Matrix(N, M, C, args.dtype, **(opts16 if args.dtype == "f16" else opts))
-    b_a = 6 if args.dtype == "f32" else 4
-    b_x = 4 if args.dtype == "f32" else 2
     info = A.info()
     log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
         f"A^T padded {info['AT']['padded']:,}")
-    F = min(int(info["fuse"]), 1 << max(0, (B - 1).bit_length()))  # slices per matrix pass
     nnz = info["A"]["nnz"]
-    bytes_A = alg_bytes(nnz, N * N, M * C, B, F, b_a)
-    bytes_AT = alg_bytes(info["AT"]["nnz"], M * C, N * N, B, F, b_a)
-    bytes_step = bytes_A + bytes_AT
-
     x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device=dev).float()
-    y = torch.empty((B, M, C), dtype=torch.float32, device=dev)
-    xb = torch.empty((B, N, N), dtype=torch.float32, device=dev)
-    ws = A.spmm_workspace(B)
-
-    def step():
-        xct.project(A, x, out=y, workspace=ws)
-        xct.backproject(A, y, out=xb, workspace=ws)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
@@ -178,34 +379,14 @@ def main():
         log(f"copy calibration: {nb} bytes read, {nb} bytes written")
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
-    xct.profile_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    xct.profile_enable(False)
-    prof = xct.profile_read()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    hs = time_products(xct, torch, A, x, args.steps, warmup=args.warmup)
+    F, ms_step = hs["fuse"], hs["ms_per_step"]
+    bytes_step = hs["bytes_step"]
     value = bytes_step / (ms_step * 1e-3) / 1e9
-    nA, msA = prof["A"]
-    nT, msT = prof["AT"]
-    # kernel: matrix entries + staged operand (storage dtype) in + FP32 sums out
-    kern_bytes_A = nnz * b_a + F * (N * N * b_x + M * C * 4)
-    kern_bytes_AT = info["AT"]["nnz"] * b_a + F * (M * C * b_x + N * N * 4)
-    launches = nA + nT
-    avg_ms = (msA + msT) / max(launches, 1)
-    achieved = (kern_bytes_A * nA + kern_bytes_AT * nT) / ((msA + msT) * 1e-3) / 1e9
-    log(f"step {ms_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {value:.1f} GB/s; "
-        f"SpMM A {msA / max(nA, 1):.3f} ms, A^T {msT / max(nT, 1):.3f} ms per launch")
+    log(f"step {ms_step:.3f} ms ({hs['wall_ms_per_step']:.3f} ms wall), {value:.1f} GB/s; "
+        f"SpMM A {hs['launch_ms']['A']:.3f} ms, A^T {hs['launch_ms']['AT']:.3f} ms per launch")
+    y = xct.project(A, x)
 
     # context: what a plain streaming read (16-byte non-temporal loads) reaches
     # on this device over 4 GiB resident in HBM
@@ -248,20 +429,21 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": f"k_spmm<{args.dtype},{F}> (A and A^T launches)",
-            "achieved": round(achieved, 2),
+            "achieved": hs["kernel_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.dtype, N, M, B,
-                                        not (args.stage_order or args.lds_bytes or args.tile_waves or args.fuse or
-                                             args.arith or
-                                             args.lane_order or args.slab_order)),
+            "frac": hs["kernel_frac"],
+            "traffic": measured_traffic(args.dtype, N, M, B, default_opts),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_ms": round(avg_ms, 4),
-            "alg_bytes_per_launch": {"A": kern_bytes_A, "AT": kern_bytes_AT},
-            "launch_ms": {"A": round(msA / max(nA, 1), 4), "AT": round(msT / max(nT, 1), 4)},
+            "avg_launch_ms": hs["avg_launch_ms"],
+            "alg_bytes_per_launch": hs["alg_bytes_per_launch"],
+            "launch_ms": hs["launch_ms"],
         },
     }
+
+    if oracle is not None:
+        log("oracle errors of the headline products")
+        out["oracle_error"] = headline_errors(oracle, xct, torch, A, N, M, C, x, y, [0, 7, 15])
 
     if args.streamed:
         # host-resident batch (the benchmark batch repeated): chunks of F slices
@@ -269,6 +451,7 @@ def main():
         # PCIe-inclusive, never the headline value
         BS = args.streamed
         log(f"streamed step ({BS} host-resident slices)")
+        b_a = BYTES_A[args.dtype]
         xh = x.cpu().repeat((BS + B - 1) // B, 1, 1)[:BS].contiguous().pin_memory()
         yh = torch.empty((BS, M, C), dtype=torch.float32, pin_memory=True)
         xbh = torch.empty((BS, N, N), dtype=torch.float32, pin_memory=True)
@@ -298,21 +481,6 @@ def main():
         it = args.cgls_iters
         yc = (y + 0.01 * float(y.abs().max()) * phantoms.noise_torch((M, C), B, 2, dev)).contiguous()
 
-        def cgls_time(Am, iters, reps=2):
-            wsc = Am.cgls_workspace(B, iters)
-            xo = torch.empty((B, N, N), dtype=torch.float32, device=dev)
-            xct.cgls(Am, yc, iters, out=xo, workspace=wsc, want_resid=False)
-            torch.cuda.synchronize()
-            best = float("inf")
-            for _ in range(reps):
-                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                s0.record()
-                xct.cgls(Am, yc, iters, out=xo, workspace=wsc, want_resid=False)
-                s1.record()
-                torch.cuda.synchronize()
-                best = min(best, s0.elapsed_time(s1) * 1e-3)
-            return best
-
         def cgls_history(Am):
             # untimed run with the per-iteration residual history ||y - A x_k|| / ||y||
             xo, res, _ = xct.cgls(Am, yc, it)
@@ -321,44 +489,23 @@ def main():
         checkpoints = [k for k in (0, 1, 2, 3, 5, 10, 20, 30, 50) if k <= it]
         log("CGLS FP32")
         A32 = A if args.dtype == "f32" else xct.Matrix(N, M, C, "f32", **opts)
-        t32 = (cgls_time(A32, it) - cgls_time(A32, 0)) / it
+        t32 = cgls_s_per_iter(xct, torch, A32, yc, it)
         x32, res32 = cgls_history(A32)
-        del A32
-        if args.dtype == "f32":
-            del A
+        A32.free()
+        A.free()
+        del A32, A
         torch.cuda.empty_cache()
         log("building FP16 matrix")
-        A16 = A if args.dtype == "f16" else xct.Matrix(N, M, C, "f16", **opts16)
+        A16 = xct.Matrix(N, M, C, "f16", **opts16)
         log("CGLS FP16 storage")
-        t16 = (cgls_time(A16, it) - cgls_time(A16, 0)) / it
+        t16 = cgls_s_per_iter(xct, torch, A16, yc, it)
         x16, res16 = cgls_history(A16)
         d16 = ((x16 - x32).flatten(1).norm(dim=1) / x32.flatten(1).norm(dim=1).clamp_min(1e-30)).max().item()
         del x32, x16
         # the FP16 operators' projection + backprojection step, for reference
-        i16 = A16.info()
-        ws16 = A16.spmm_workspace(B)
-        for _ in range(2):
-            xct.project(A16, x, out=y, workspace=ws16)
-        torch.cuda.synchronize()
-        xct.profile_enable(True)
-        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        f0.record()
-        for _ in range(args.steps):
-            xct.project(A16, x, out=y, workspace=ws16)
-            xct.backproject(A16, y, out=xb, workspace=ws16)
-        f1.record()
-        torch.cuda.synchronize()
-        xct.profile_enable(False)
-        p16 = xct.profile_read()
-        ms16 = f0.elapsed_time(f1) / args.steps
-        kb16 = {w: i16[w]["nnz"] * 4 + F * (N * N * 2 + M * C * 4) for w in ("A", "AT")}
-        ach16 = (kb16["A"] * p16["A"][0] + kb16["AT"] * p16["AT"][0]) / ((p16["A"][1] + p16["AT"][1]) * 1e-3) / 1e9
-        b16 = alg_bytes(i16["A"]["nnz"], N * N, M * C, B, F, 4) + alg_bytes(i16["AT"]["nnz"], M * C, N * N, B, F, 4)
-        out["fp16_step"] = {"ms_per_step": round(ms16, 4), "GBps": round(b16 / (ms16 * 1e-3) / 1e9, 2),
-                            "kernel_GBps": round(ach16, 2), "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4),
-                            "launch_ms": {"A": round(p16["A"][1] / max(p16["A"][0], 1), 4),
-                                          "AT": round(p16["AT"][1] / max(p16["AT"][0], 1), 4)},
-                            "padded_A": i16["A"]["padded"], "padded_AT": i16["AT"]["padded"]}
+        s16 = time_products(xct, torch, A16, x, args.steps)
+        out["fp16_step"] = {k: s16[k] for k in ("ms_per_step", "GBps", "kernel_GBps", "kernel_frac", "launch_ms",
+                                                 "padded_A", "padded_AT")}
         # convergence against time: median relative residual over the slices
         # after k iterations, reached at k * s/iter
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),
@@ -367,10 +514,9 @@ def main():
                                            "fp32": [float(np.median(res32[k])) for k in checkpoints],
                                            "fp16": [float(np.median(res16[k])) for k in checkpoints]},
                        "fp16_vs_fp32_rel_l2_max": round(d16, 6),
-                       "build_s_f16": round(A16.info()["build_seconds"], 3)}
+                       "build_s_f16": s16["build_s"]}
         log(f"CGLS s/iter FP32 {t32 * 1e3:.3f} ms, FP16 {t16 * 1e3:.3f} ms")
-        # the generic gradient solver of Eq. (1) (x >= 0, TV) on the same
-        # FP16 operators: torch autograd around the projection pair
+        # the gradient solver of Eq. (1) (x >= 0, TV) on the same FP16 operators
         log("projected gradient FP16")
         lam, eps, pg_it = 0.1, 0.05, 5
         tau = 0.95 / pgrad.lipschitz(A16, lam, eps, 10)
@@ -383,13 +529,100 @@ def main():
         torch.cuda.synchronize()
         tpg = g0.elapsed_time(g1) * 1e-3 / pg_it
         out["projected_gradient"] = {"iters": pg_it, "lam": lam, "eps": eps, "fp16_s_per_iter": round(tpg, 6),
-                                     "vs_spmm_pair": round(tpg / (ms16 * 1e-3), 3)}
-        del A16
+                                     "vs_spmm_pair": round(tpg / (s16["ms_per_step"] * 1e-3), 3)}
+        A16.free()
+        del A16, yc
+    else:
+        A.free()
+        del A
+    del y
+    torch.cuda.empty_cache()
 
-    if not args.no_cpu:
+    traced = None
+    if not args.no_large:
+        # 64 slices 2048^2, 1500 angles, 2048 channels (FP32, FP16, BF16)
+        N4, M4, B4, it4 = 2048, 1500, 64, 30
+        sl4 = [17, 40]
+        log("64 x 2048^2 x 1500: FP32 matrix")
+        x4 = phantoms.ellipsoid_phantom(N4, B4, 60, seed=4, device=dev).float()
+        c4 = {"workload": f"{B4} slices {N4}x{N4}, {M4} angles over [0,pi), {N4} channels, 60-ellipsoid phantom, "
+                          f"1% noise; CGLS {it4} iterations"}
+        y4 = None
+        for dt in ("f32", "f16", "bf16"):
+            A4 = xct.Matrix(N4, M4, N4, dt)
+            if y4 is None:
+                y4 = xct.project(A4, x4)
+                y4 = (y4 + 0.01 * float(y4.abs().max()) * phantoms.noise_torch((M4, N4), B4, 4, dev)).contiguous()
+                if oracle is not None:
+                    # the oracle's CGLS history on 2 slices, on the host meanwhile
+                    y2 = y4[sl4].double().cpu().numpy().reshape(len(sl4), -1)
+                    traced = TracedOracleCgls(oracle, N4, M4, N4, y2, 3, max(1, threads - 2))
+                    traced.start()
+            r = time_products(xct, torch, A4, x4, 3, warmup=1)
+            r["cgls_s_per_iter"] = round(cgls_s_per_iter(xct, torch, A4, y4, it4), 6)
+            _, res4, _ = xct.cgls(A4, y4, it4)
+            r["residual_median_final"] = float(np.median(res4[-1]))
+            if oracle is not None:
+                r["_iterates"] = gpu_cgls_iterates(xct, A4, y4[sl4].contiguous(), 3)
+            c4[dt] = r
+            log(f"  {dt}: step {r['ms_per_step']:.2f} ms, kernel {100 * r['kernel_frac']:.1f}% of peak, "
+                f"CGLS {1e3 * r['cgls_s_per_iter']:.2f} ms/iter")
+            A4.free()
+            del A4
+            torch.cuda.empty_cache()
+        c4["fp16_cgls_speedup"] = round(c4["f32"]["cgls_s_per_iter"] / c4["f16"]["cgls_s_per_iter"], 3)
+        out["c64x2048"] = c4
+        del x4, y4
+        torch.cuda.empty_cache()
+
+        # 128 slices 2816^2, 2250 angles, 2816 channels, FP16 (the large single-GPU share)
+        N5, M5, B5, it5 = 2816, 2250, 128, 20
+        log("128 x 2816^2 x 2250: FP16 matrix")
+        A5 = xct.Matrix(N5, M5, N5, "f16")
+        x5 = phantoms.ellipsoid_phantom(N5, B5, 200, seed=5, device=dev, texture=0.05).float()
+        r = time_products(xct, torch, A5, x5, 2, warmup=1)
+        y5 = xct.project(A5, x5)
+        y5 = (y5 + 0.01 * float(y5.abs().max()) * phantoms.noise_torch((M5, N5), B5, 5, dev)).contiguous()
+        del x5
+        r["cgls_20_s"] = round(cgls_seconds(xct, torch, A5, y5, it5, reps=1), 4)
+        r["cgls_s_per_iter"] = round((r["cgls_20_s"] - cgls_seconds(xct, torch, A5, y5, 0, reps=1)) / it5, 6)
+        log(f"  f16: step {r['ms_per_step']:.2f} ms, kernel {100 * r['kernel_frac']:.1f}% of peak, "
+            f"{it5} CGLS iterations {r['cgls_20_s']:.2f} s")
+        out["c128x2816"] = {"workload": f"{B5} slices {N5}x{N5}, {M5} angles over [0,pi), {N5} channels, "
+                                        f"200 ellipsoids + texture, 1% noise; CGLS {it5} iterations", "f16": r}
+        A5.free()
+        del A5, y5
+        torch.cuda.empty_cache()
+
+    if oracle is not None:
+        oracle.set_threads(threads)
+        log("CGLS against the oracle per iteration, 2 slices of 512^2 x 360")
+        out["cgls_vs_oracle_512"] = cgls_errors_512(oracle, xct, torch, phantoms, dev)
+        if traced is not None:
+            log("waiting for the oracle's 2048^2 CGLS")
+            traced.join()
+            oracle.set_threads(threads)
+            c4 = out["c64x2048"]
+            rep = {"slices": sl4, "k": [1, 2, 3], "oracle_seconds": round(traced.seconds, 1)}
+            if traced.result is not None:
+                xho, reso = traced.result
+                for dt in ("f32", "f16", "bf16"):
+                    xg, resg = c4[dt].pop("_iterates")
+                    rep[dt] = [round(e, 8) for e in per_iteration_errors(xg, xho)]
+                    rep[dt + "_residual_rel_dev_max"] = float((abs(resg - reso) / reso).max())
+                rep["f16_within_1e-3_through_k"] = holds_through(rep["f16"], 1e-3)
+            else:
+                rep["error"] = traced.error
+                for dt in ("f32", "f16", "bf16"):
+                    c4[dt].pop("_iterates", None)
+            c4["cgls_vs_oracle"] = rep
         log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(N, M, C, B, x.double().cpu().numpy().reshape(B, -1), bytes_step,
-                                           args.cpu_seconds)
+        ys = np.random.default_rng(1).random((B, M * C))
+        out["cpu_baseline"] = cpu_baseline(oracle, N, M, C, B, x.double().cpu().numpy().reshape(B, -1), ys,
+                                           bytes_step, args.cpu_seconds, threads)
+    elif "c64x2048" in out:
+        for dt in ("f32", "f16", "bf16"):
+            out["c64x2048"][dt].pop("_iterates", None)
     print(json.dumps(out), flush=True)
 
 

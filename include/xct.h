@@ -71,7 +71,8 @@ enum {
 typedef struct {
     int tile_waves; /* row tiles (64 rows each) per workgroup: 1..16 (one wavefront each) or 32
                        (16 wavefronts holding two row tiles each); default 16 */
-    int fuse;       /* largest number of slices fused per matrix pass (F); 1,2,4,8 or 16; default 16 */
+    int fuse;       /* largest number of slices fused per matrix pass (F); 1, 2, 4, 8, 16 or 32
+                       (32: F16/BF16 matrices with tile_waves <= 16 only); default 16 */
     int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input
                        (T = lds_bytes / (64 * F * element size) input tiles, at most 1024);
                        default: all of the device's LDS per workgroup (160 KiB on gfx950) */
@@ -95,7 +96,8 @@ typedef struct {
 
 /* Statistics of one operator (A or A^T). */
 typedef struct {
-    int64_t nnz;          /* structural nonzeros */
+    int64_t nnz;          /* structural nonzeros: chord lengths above 1e-9 that do not round
+                             to zero in the stored format (FP16 drops lengths <= 2^-25) */
     int64_t padded;       /* stored entries including ELL padding */
     int64_t bytes;        /* device bytes of the operator (entries + maps) */
     int64_t stages;       /* total staging rounds over all workgroups */
@@ -190,7 +192,9 @@ size_t xct_stream_workspace_bytes(const xct_matrix *A, int which, int chunk, xct
  *              workspace belongs to compute_stream's order: the copy streams first
  *              wait for the work already enqueued there.
  * Returns after every result is in y_host (the three streams are drained,
- * also on error).  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ * also on error).  The handle keeps the call's seven events from its first
+ * streamed call on (released with it); streamed calls that share a handle
+ * run one at a time.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
  */
 int xct_project_streamed(const xct_matrix *A, const void *x_host, void *y_host, int batch, int chunk,
                          xct_dtype io, void *workspace, void *compute_stream, void *h2d_stream,
@@ -202,6 +206,15 @@ int xct_project_streamed(const xct_matrix *A, const void *x_host, void *y_host, 
 int xct_backproject_streamed(const xct_matrix *A, const void *y_host, void *x_host, int batch, int chunk,
                              xct_dtype io, void *workspace, void *compute_stream, void *h2d_stream,
                              void *d2h_stream);
+
+/*
+ * Number of NaN or infinite elements among the n elements of the device
+ * array v of dtype dt, written to *count (device, int64, 8-B aligned) on
+ * `stream` (no host sync).  The products assume finite inputs (a
+ * non-finite element spreads to every output it reaches); callers check
+ * untrusted inputs with this.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
+ */
+int xct_count_nonfinite(const void *v, int64_t n, xct_dtype dt, int64_t *count, void *stream);
 
 /* Device workspace needed by xct_cgls for `batch` slices and `iters` iterations. */
 size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
@@ -215,9 +228,11 @@ size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
  *   iters      >= 0
  *   workspace  device, >= xct_cgls_workspace_bytes(A, batch, iters) bytes, 256-B aligned
  *   resid      nullable host, [iters+1][batch]: ||y_b - A x_k|| / ||y_b||
- *              (0 when y_b = 0)
+ *              (0 when y_b = 0; NaN for a slice of status 2)
  *   status     nullable host, [batch]: 1 when the slice stopped early
- *              because gamma = ||A^T r||^2 or delta = ||A p||^2 became 0,
+ *              because gamma = ||A^T r||^2 or delta = ||A p||^2 became 0;
+ *              2 when y_b holds a NaN or an infinity (the slice is not
+ *              solved and x_b stays 0; the other slices are unaffected);
  *              else 0
  * Solver vectors are FP32 and the per-slice scalars FP64.  With an F16/BF16
  * matrix the operand of each product is max-norm scaled and rounded to
@@ -281,8 +296,20 @@ int xct_profile_read(int64_t *launches, double *ms);
 /* Measurement utility: streaming-read bandwidth of the device (GB/s, 1e9 B/s)
  * over the caller's device buffer of `bytes` bytes (>= 16; read only),
  * `reps` timed passes after one untimed pass, on `stream`; blocks until done.
- * The reference ceiling for the SpMM's matrix stream; not part of the method. */
+ * Allocates nothing per call (its two timing events are created once per
+ * device; calls from several threads run one at a time).  The reference
+ * ceiling for the SpMM's matrix stream; not part of the method. */
 int xct_read_bandwidth(const void *buf, int64_t bytes, int reps, double *gbps, void *stream);
+
+/*
+ * Device memory the library holds (every matrix handle's buffers): the
+ * number of buffers and their total bytes (host outputs).  Build failures
+ * release everything they took, so these return to their previous values
+ * after any failed xct_build_matrix.  Failure injection for tests: with
+ * XCT_FAULT_ALLOC=n in the environment, the n-th device allocation counted
+ * from when the variable took its current value fails with XCT_ERR_OOM.
+ */
+int xct_device_memory(int64_t *buffers, int64_t *bytes);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *xct_last_error(void);

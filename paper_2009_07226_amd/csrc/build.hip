@@ -22,8 +22,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <new>
 #include <numeric>
+#include <unordered_map>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -39,6 +43,45 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 int fail(int code, const std::string &msg) {
     g_last_error = msg;
     return code;
+}
+
+// ---- the library's device allocations ---------------------------------------
+//
+// Every device buffer the library takes goes through dev_alloc and dev_free,
+// which keep the live buffers and their sizes (xct_device_memory reports
+// them, for leak checks).  Failure injection for the tests of error paths:
+// with XCT_FAULT_ALLOC=n in the environment, the n-th allocation counted
+// from when the variable took its current value fails as out of memory.
+static std::mutex g_alloc_mu;
+static std::unordered_map<void *, size_t> g_alloc_live;
+static int64_t g_alloc_count = 0;
+static std::string g_fault_value;
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    const char *env = std::getenv("XCT_FAULT_ALLOC");
+    const std::string cur = env ? env : "";
+    if (cur != g_fault_value) {
+        g_fault_value = cur;
+        g_alloc_count = 0;
+    }
+    ++g_alloc_count;
+    if (!cur.empty() && std::atoll(cur.c_str()) == g_alloc_count) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) g_alloc_live[*p] = bytes;
+    return e;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        g_alloc_live.erase(p);
+    }
+    (void)hipFree(p);
 }
 
 // ---- rounding FP64 -> 16-bit, nearest-even, single rounding -------------
@@ -142,6 +185,7 @@ struct ProjRows {
     int rowTW;                 // sinogram tiles per tile row
     int inTW;                  // voxel tiles per tile row
     int lanes;                 // lane_slot order
+    double zero_below;         // lengths at or below this round to zero in the stored format: not entries
     template <class V>
     __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
@@ -150,7 +194,7 @@ struct ProjRows {
         const int c = (coord % rowTW) * kTile + (o & 7);
         if (k >= M || c >= C) return;
         trace_ray(N, M, C, k, c, [&](int i, int j, double len) {
-            v(key_of[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
+            if (len > zero_below) v(key_of[(i >> 3) * inTW + (j >> 3)], ((i & 7) << 3) | (j & 7), len);
         });
     }
 };
@@ -162,6 +206,7 @@ struct BackRows {
     int rowTW;
     int inTW;                  // sinogram tiles per tile row
     int lanes;                 // lane_slot order
+    double zero_below;         // as ProjRows
     template <class V>
     __device__ __forceinline__ void run(int64_t rt, int lane, const int32_t *key_of, V &&v) const {
         const int coord = row_coord[rt];
@@ -170,7 +215,7 @@ struct BackRows {
         const int j = (coord % rowTW) * kTile + (o & 7);
         if (i >= N || j >= N) return;
         trace_voxel(N, M, C, i, j, [&](int k, int c, double len) {
-            v(key_of[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
+            if (len > zero_below) v(key_of[(k >> 3) * inTW + (c >> 3)], ((k & 7) << 3) | (c & 7), len);
         });
     }
 };
@@ -676,13 +721,13 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        dev_free(p);
     }
 };
 
 template <class T>
 static int upload(T **dst, const std::vector<T> &src) {
-    XCT_HIP_TRY(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(1, src.size())));
+    XCT_HIP_TRY(dev_alloc((void **)dst, sizeof(T) * std::max<size_t>(1, src.size())));
     if (!src.empty()) XCT_HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
     return XCT_OK;
 }
@@ -783,7 +828,7 @@ struct DevOrder {
     void *bufs[3] = {nullptr, nullptr, nullptr};
     ~DevOrder() {
         for (void *p : bufs)
-            if (p) (void)hipFree(p);
+            dev_free(p);
     }
 };
 
@@ -807,7 +852,7 @@ static int upload_order(const HostOrder &h, int64_t n_in, DevOrder &d) {
 static void free_op(OpPlan &op) {
     void *ps[] = {op.blk_stage, op.blk_tile, op.tile_list, op.slab, op.ent};
     for (void *p : ps)
-        if (p) (void)hipFree(p);
+        dev_free(p);
     op = OpPlan();
 }
 
@@ -839,8 +884,8 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
 
     const int nb = op.n_blocks;
     DevBuf d_nt, d_nnz, d_len, d_err;
-    XCT_HIP_TRY(hipMalloc(&d_nt.p, sizeof(int32_t) * nb));
-    XCT_HIP_TRY(hipMalloc(&d_nnz.p, sizeof(int64_t) * nb));
+    XCT_HIP_TRY(dev_alloc(&d_nt.p, sizeof(int32_t) * nb));
+    XCT_HIP_TRY(dev_alloc(&d_nnz.p, sizeof(int64_t) * nb));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_footprint<Rows>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_mark));
     hipLaunchKernelGGL(k_footprint<Rows>, dim3(nb), dim3(nthr), smem_mark, st, rows, ord, n_row_tiles, nwords, W,
@@ -870,11 +915,11 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     if (!rc) rc = upload(&op.blk_stage, blk_stage);
     if (rc) return rc;
     // 4 entries of padding: the SpMM reads the list four entries at a time
-    XCT_HIP_TRY(hipMalloc((void **)&op.tile_list, sizeof(int32_t) * (op.n_list + 4)));
+    XCT_HIP_TRY(dev_alloc((void **)&op.tile_list, sizeof(int32_t) * (op.n_list + 4)));
     XCT_HIP_TRY(hipMemsetAsync(op.tile_list, 0, sizeof(int32_t) * (op.n_list + 4), st));
     const int64_t nlen = op.n_stages * W;
-    XCT_HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * std::max<int64_t>(1, nlen)));
-    XCT_HIP_TRY(hipMalloc(&d_err.p, sizeof(int)));
+    XCT_HIP_TRY(dev_alloc(&d_len.p, sizeof(int32_t) * std::max<int64_t>(1, nlen)));
+    XCT_HIP_TRY(dev_alloc(&d_err.p, sizeof(int)));
     XCT_HIP_TRY(hipMemsetAsync(d_err.p, 0, sizeof(int), st));
     XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_plan<Rows>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)smem_win));
@@ -909,7 +954,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     // at least one group: the kernel's prefetch may re-read group 0
     const size_t nent = (size_t)std::max<int64_t>(1, op.n_groups) * kTileSlots * kGroup;
     const size_t ent_bytes = nent * (vdt == XCT_F32 ? 6 : 4);
-    XCT_HIP_TRY(hipMalloc(&op.ent, ent_bytes));
+    XCT_HIP_TRY(dev_alloc(&op.ent, ent_bytes));
     XCT_HIP_TRY(hipMemsetAsync(op.ent, 0, ent_bytes, st));
     if (vdt == XCT_F32) {
         op.slot = (uint16_t *)op.ent;
@@ -961,14 +1006,14 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
                 }
         }
         DevBuf d_done;
-        XCT_HIP_TRY(hipMalloc(&d_done.p, sizeof(unsigned long long)));
+        XCT_HIP_TRY(dev_alloc(&d_done.p, sizeof(unsigned long long)));
         XCT_HIP_TRY(hipMemsetAsync(d_done.p, 0, sizeof(unsigned long long), st));
         std::vector<DevBuf> d_ids(4);
         for (int k = 0; k < 4; ++k) {
             if (ids[k].empty()) continue;
             const int64_t bc = std::min(bucket_cap[k], cap);
             const size_t smem_b = fixed_b + step * (size_t)bc;
-            XCT_HIP_TRY(hipMalloc(&d_ids[k].p, sizeof(int32_t) * ids[k].size()));
+            XCT_HIP_TRY(dev_alloc(&d_ids[k].p, sizeof(int32_t) * ids[k].size()));
             XCT_HIP_TRY(hipMemcpyAsync(d_ids[k].p, ids[k].data(), sizeof(int32_t) * ids[k].size(),
                                        hipMemcpyHostToDevice, st));
             auto bal = [&](auto kern) -> int {
@@ -1007,13 +1052,25 @@ using namespace xct;
 
 extern "C" const char *xct_last_error(void) { return g_last_error.c_str(); }
 
+extern "C" int xct_device_memory(int64_t *buffers, int64_t *bytes) {
+    if (!buffers || !bytes) return fail(XCT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    int64_t b = 0;
+    for (const auto &kv : g_alloc_live) b += (int64_t)kv.second;
+    *buffers = (int64_t)g_alloc_live.size();
+    *bytes = b;
+    return XCT_OK;
+}
+
 extern "C" void xct_free_matrix(xct_matrix *m) {
     if (!m) return;
     free_op(m->A);
     free_op(m->AT);
     void *ps[] = {m->vol.rank_of, m->vol.coord_of, m->sino.rank_of, m->sino.coord_of};
     for (void *p : ps)
-        if (p) (void)hipFree(p);
+        dev_free(p);
+    for (hipEvent_t e : m->stream_ev)
+        if (e) (void)hipEventDestroy(e);
     delete m;
 }
 
@@ -1033,7 +1090,10 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     const int F = o.fuse ? o.fuse : 16;
     int lds = o.lds_bytes;
     if (W < 1 || (W > 16 && W != 32)) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16] or 32");
-    if (F != 1 && F != 2 && F != 4 && F != 8 && F != 16) return fail(XCT_ERR_INVALID, "fuse must be 1, 2, 4, 8 or 16");
+    if (F != 1 && F != 2 && F != 4 && F != 8 && F != 16 && F != 32)
+        return fail(XCT_ERR_INVALID, "fuse must be 1, 2, 4, 8, 16 or 32");
+    if (F == 32 && (value_dtype == XCT_F32 || W > 16))
+        return fail(XCT_ERR_UNSUPPORTED, "32 fused slices need a 16-bit matrix and at most 16 row tiles per workgroup");
     const int per_tile = kTileSlots * F * elem_bytes(value_dtype);
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
@@ -1053,8 +1113,14 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         return fail(XCT_ERR_UNSUPPORTED, "FP16 arithmetic needs an FP16 matrix");
     const int row_bytes = F * elem_bytes(value_dtype);
     const int lanes = o.lane_order;
+    // A length that rounds to zero in the stored format contributes nothing
+    // and is not an entry (FP16: lengths up to 2^-25, the half-way point to
+    // the smallest subnormal, round to zero; BF16 and FP32 keep every length
+    // above the geometric cut-off).
+    const double zero_below = value_dtype == XCT_F16 ? 0x1p-25 : 0.0;
     auto t0 = std::chrono::steady_clock::now();
-    xct_matrix *m = new xct_matrix();
+    xct_matrix *m = new (std::nothrow) xct_matrix();
+    if (!m) return fail(XCT_ERR_OOM, "host allocation failed");
     m->n = n;
     m->M = n_angles;
     m->C = n_channels;
@@ -1062,34 +1128,42 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     m->fuse = F;
     m->remap = o.xcd_remap >= 0 ? 1 : 0;
     hipStream_t st = (hipStream_t)stream;
-    int rc = make_grid(m->vol, n, n);
-    if (!rc) rc = make_grid(m->sino, n_angles, n_channels);
-    if (!rc) {
-        ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.TW, lanes};
-        HostOrder ho;
-        const int nb = (int)((m->sino.n_tiles + W - 1) / W);
-        if (o.stage_order == 1)
-            order_hilbert(m->vol, ho);
-        else
-            order_sweep_proj(m, W, nb, ho);
-        DevOrder dord;
-        rc = upload_order(ho, m->vol.n_tiles, dord);
-        if (!rc)
-            rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, value_dtype, row_bytes,
-                          o.slab_order == 0, st);
-    }
-    if (!rc) {
-        BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW, lanes};
-        HostOrder ho;
-        if (o.stage_order == 1)
-            order_hilbert(m->sino, ho);
-        else
-            order_raster(m->sino, ho);
-        DevOrder dord;
-        rc = upload_order(ho, m->sino.n_tiles, dord);
-        if (!rc)
-            rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, row_bytes,
-                          o.slab_order == 0, st);
+    // host containers may throw; the C ABI returns a status instead
+    int rc = XCT_OK;
+    try {
+        rc = make_grid(m->vol, n, n);
+        if (!rc) rc = make_grid(m->sino, n_angles, n_channels);
+        if (!rc) {
+            ProjRows pr{n, n_angles, n_channels, m->sino.coord_of, m->sino.TW, m->vol.TW, lanes, zero_below};
+            HostOrder ho;
+            const int nb = (int)((m->sino.n_tiles + W - 1) / W);
+            if (o.stage_order == 1)
+                order_hilbert(m->vol, ho);
+            else
+                order_sweep_proj(m, W, nb, ho);
+            DevOrder dord;
+            rc = upload_order(ho, m->vol.n_tiles, dord);
+            if (!rc)
+                rc = build_op(m->A, pr, dord.d, m->sino.n_tiles, m->vol.n_tiles, W, T, value_dtype, row_bytes,
+                              o.slab_order == 0, st);
+        }
+        if (!rc) {
+            BackRows br{n, n_angles, n_channels, m->vol.coord_of, m->vol.TW, m->sino.TW, lanes, zero_below};
+            HostOrder ho;
+            if (o.stage_order == 1)
+                order_hilbert(m->sino, ho);
+            else
+                order_raster(m->sino, ho);
+            DevOrder dord;
+            rc = upload_order(ho, m->sino.n_tiles, dord);
+            if (!rc)
+                rc = build_op(m->AT, br, dord.d, m->vol.n_tiles, m->sino.n_tiles, W, T, value_dtype, row_bytes,
+                              o.slab_order == 0, st);
+        }
+    } catch (const std::bad_alloc &) {
+        rc = fail(XCT_ERR_OOM, "host allocation failed during the build");
+    } catch (const std::exception &e) {
+        rc = fail(XCT_ERR_INTERNAL, std::string("build: ") + e.what());
     }
     m->A.arith16 = m->AT.arith16 = o.arith == 1 ? 1 : 0;
     if (rc) {
@@ -1154,8 +1228,20 @@ static float bf16_bits_to_float(uint16_t h) {
     return v;
 }
 
+static int matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t *cols, float *vals, int64_t cap,
+                         int64_t *count);
+
 extern "C" int xct_matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t *cols, float *vals,
                                  int64_t cap, int64_t *count) {
+    try {  // host copies of the operator may not fit: a status, never an exception
+        return matrix_to_coo(m, which, rows, cols, vals, cap, count);
+    } catch (const std::bad_alloc &) {
+        return fail(XCT_ERR_OOM, "host allocation failed while decoding the operator");
+    }
+}
+
+static int matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t *cols, float *vals, int64_t cap,
+                         int64_t *count) {
     if (!m || !rows || !cols || !vals || !count) return fail(XCT_ERR_INVALID, "NULL argument");
     if (which != 0 && which != 1) return fail(XCT_ERR_INVALID, "which must be 0 (A) or 1 (A^T)");
     const OpPlan &op = which ? m->AT : m->A;

@@ -19,7 +19,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <vector>
 
 #include "common.hpp"
 
@@ -75,9 +74,9 @@ static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base,
     c.sum = (double *)take(sizeof(double) * c.Bp);
     c.stopped = (int32_t *)take(sizeof(int32_t) * c.Bp);
     c.resid = (double *)take(sizeof(double) * (size_t)(iters + 1) * c.Bp);
-    c.amax = (uint32_t *)take(sizeof(uint32_t) * 16);
-    c.scale = (float *)take(sizeof(float) * 16);
-    c.inv = (float *)take(sizeof(float) * 16);
+    c.amax = (uint32_t *)take(sizeof(uint32_t) * (size_t)c.Bp);
+    c.scale = (float *)take(sizeof(float) * kMaxFuse);
+    c.inv = (float *)take(sizeof(float) * kMaxFuse);
     if (w) *w = c;
     return off;
 }
@@ -106,39 +105,10 @@ __global__ void k_sqnorm(const float *v, int64_t n, int F, double *part) {
     block_partial(acc, F, part);
 }
 
-// x += alpha p ; (volume)
-__global__ void k_axpy_vol(float *x, const float *p, int64_t n, int F, const double *alpha) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float a = (float)alpha[i & (F - 1)];
-        x[i] = fmaf(a, p[i], x[i]);
-    }
-}
-
-// r -= alpha q, with block partials of |r|^2 (sinogram)
-__global__ void k_axpy_res(float *r, const float *q, int64_t n, int F, const double *alpha, double *part) {
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float a = (float)alpha[i & (F - 1)];
-        const float t = fmaf(-a, q[i], r[i]);
-        r[i] = t;
-        acc += (double)t * (double)t;
-    }
-    block_partial(acc, F, part);
-}
-
-// p = s + beta p
-__global__ void k_xpby(float *p, const float *s, int64_t n, int F, const double *beta) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float bt = (float)beta[i & (F - 1)];
-        p[i] = fmaf(bt, p[i], s[i]);
-    }
-}
-
-// Per-slice max |v| of an internal-layout group vector.
-__global__ void k_absmax_int(const float *v, int64_t n, int F, uint32_t *amax) {
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(v[i]));
+// Per-slice max of non-negative floats across the grid (their bits order
+// like the values); the grid stride is a multiple of F, so each thread's
+// values all belong to one slice.
+__device__ __forceinline__ void block_max(float m, int F, uint32_t *amax) {
     __shared__ float red[kVecThreads];
     red[threadIdx.x] = m;
     __syncthreads();
@@ -146,6 +116,56 @@ __global__ void k_absmax_int(const float *v, int64_t n, int F, uint32_t *amax) {
         for (int t = threadIdx.x + F; t < kVecThreads; t += F) m = fmaxf(m, red[t]);
         atomicMax(&amax[threadIdx.x], __float_as_uint(m));
     }
+}
+
+// r -= alpha q, with block partials of |r|^2 (sinogram) and, when amax is
+// given, the per-slice max |r| (the next product's operand scale)
+__global__ void k_axpy_res(float *r, const float *q, int64_t n, int F, const double *alpha, double *part,
+                           uint32_t *amax) {
+    double acc = 0.0;
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float a = (float)alpha[i & (F - 1)];
+        const float t = fmaf(-a, q[i], r[i]);
+        r[i] = t;
+        acc += (double)t * (double)t;
+        m = fmaxf(m, fabsf(t));
+    }
+    block_partial(acc, F, part);
+    if (amax) block_max(m, F, amax);
+}
+
+// x += alpha p, then p = s + beta p, in one pass (the iterate's update is
+// deferred to here from the step where alpha is found: p is unchanged in
+// between); when amax is given, also the per-slice max |p| of the new p
+__global__ void k_update_xp(float *x, float *p, const float *s, int64_t n, int F, const double *alpha,
+                            const double *beta, uint32_t *amax) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float a = (float)alpha[i & (F - 1)], bt = (float)beta[i & (F - 1)];
+        const float pv = p[i];
+        if (a != 0.f) x[i] = fmaf(a, pv, x[i]);  // a stopped slice keeps its iterate, also if p is not finite
+        const float t = fmaf(bt, pv, s[i]);
+        p[i] = t;
+        m = fmaxf(m, fabsf(t));
+    }
+    if (amax) block_max(m, F, amax);
+}
+
+// Per-slice max |v| of an internal-layout group vector (the solver's first
+// operands; later ones get their max from the kernel that produces them).
+__global__ void k_absmax_int(const float *v, int64_t n, int F, uint32_t *amax) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(v[i]));
+    block_max(m, F, amax);
+}
+
+// Clear n words (a kernel rather than a memset node, so the solver can be
+// captured into a graph).
+__global__ void k_zero_words(uint32_t *v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 0u;
 }
 
 __device__ __forceinline__ uint32_t to16(float v, int fmt) {
@@ -194,9 +214,11 @@ __global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, do
     const double v = sum[b];
     switch (mode) {
         case kSetYY:
+            // a slice whose sinogram holds a non-finite value is not solved
+            // (status 2, x stays 0, residuals NaN); the others are unaffected
             yy[b] = v;
-            stopped[b] = 0;
-            resid_row[b] = v > 0.0 ? 1.0 : 0.0;
+            stopped[b] = isfinite(v) ? 0 : 2;
+            resid_row[b] = !isfinite(v) ? v - v : (v > 0.0 ? 1.0 : 0.0);
             break;
         case kSetGamma:
             gamma[b] = v;
@@ -213,7 +235,7 @@ __global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, do
             break;
         }
         case kSetResid:
-            resid_row[b] = yy[b] > 0.0 ? sqrt(v / yy[b]) : 0.0;
+            resid_row[b] = stopped[b] == 2 ? yy[b] - yy[b] : (yy[b] > 0.0 ? sqrt(v / yy[b]) : 0.0);
             break;
         case kSetBeta:
             if (stopped[b]) {
@@ -251,8 +273,20 @@ struct Cgls {
         return XCT_OK;
     }
 
+    // Per-slice max |v| of every group of an operand vector into amax (the
+    // solver's first operands; the updates produce it for later ones).
+    int absmax(const float *v, int64_t n) {
+        for (int g = 0; g < w.n_mb; ++g)
+            hipLaunchKernelGGL(k_absmax_int, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, v + (int64_t)g * n, n, w.F,
+                               w.amax + (int64_t)g * w.F);
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
+
     // One product (dir 0: q = A p, dir 1: s = A^T r) for every group, with
-    // the per-block squared-output partials, then their per-slice sums.
+    // the per-block squared-output partials, then their per-slice sums.  With
+    // a 16-bit matrix, amax holds the operand's per-slice max |v| (cleared
+    // here once read).
     int product(int dir) {
         const OpPlan &op = dir ? m->AT : m->A;
         const int64_t nin = dir ? w.ns : w.nv, nout = dir ? w.nv : w.ns;
@@ -264,9 +298,7 @@ struct Cgls {
             const float *scale = nullptr;
             if (m->vdt != XCT_F32) {
                 const int gg = vec_grid(nin);
-                hipLaunchKernelGGL(k_absmax_int, dim3(gg), dim3(kVecThreads), 0, st, (const float *)gin, nin, w.F, w.amax);
-                XCT_HIP_TRY(hipGetLastError());
-                int rc0 = launch_pow2_scale(w.amax, w.F, w.scale, w.inv, st);
+                int rc0 = launch_pow2_scale(w.amax + (int64_t)g * w.F, w.F, w.scale, w.inv, st);
                 if (rc0) return rc0;
                 hipLaunchKernelGGL(k_cast16, dim3(gg), dim3(kVecThreads), 0, st, (const float *)gin, nin, w.F,
                                    (const float *)w.inv, (uint16_t *)w.op16, (int)m->vdt);
@@ -306,13 +338,16 @@ extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, f
     hipStream_t st = c.st;
     const int gv = c.vec_grid(w.nv), gs = c.vec_grid(w.ns);
     int rc;
-    XCT_HIP_TRY(hipMemsetAsync(w.amax, 0, sizeof(uint32_t) * 16, st));
+    const bool narrow = m->vdt != XCT_F32;  // 16-bit operands: per-slice max of each product's input
+    uint32_t *amax = narrow ? w.amax : nullptr;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, w.amax, (int64_t)w.Bp);
     // r = y ; x = 0 ; yy = |y|^2
     for (int g = 0; g < w.n_mb; ++g) {
         rc = launch_to_internal(m->sino, y, y_dtype, batch, g * w.F, w.F, w.r + (int64_t)g * w.ns, XCT_F32, nullptr, st);
         if (rc) return rc;
     }
-    XCT_HIP_TRY(hipMemsetAsync(w.x, 0, sizeof(float) * w.nv * w.n_mb, st));
+    hipLaunchKernelGGL(k_zero_words, dim3(gv), dim3(kVecThreads), 0, st, (uint32_t *)w.x, w.nv * w.n_mb);
+    XCT_HIP_TRY(hipGetLastError());
     for (int g = 0; g < w.n_mb; ++g) {
         hipLaunchKernelGGL(k_sqnorm, dim3(gs), dim3(kVecThreads), 0, st, (const float *)(w.r + (int64_t)g * w.ns), w.ns,
                            w.F, w.dotp + (int64_t)g * kVecBlocks * w.F);
@@ -321,45 +356,41 @@ extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, f
     if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
     if ((rc = c.scalars(kSetYY, w.resid))) return rc;
     // s = A^T r ; gamma = |s|^2 ; p = s
+    if (narrow && (rc = c.absmax(w.r, w.ns))) return rc;
     if ((rc = c.product(1))) return rc;
     if ((rc = c.scalars(kSetGamma, nullptr))) return rc;
     XCT_HIP_TRY(hipMemcpyAsync(w.p, w.s, sizeof(float) * w.nv * w.n_mb, hipMemcpyDeviceToDevice, st));
+    if (narrow && (rc = c.absmax(w.p, w.nv))) return rc;
     for (int k = 0; k < iters; ++k) {
         if ((rc = c.product(0))) return rc;  // q = A p, delta
         if ((rc = c.scalars(kSetAlpha, nullptr))) return rc;
-        for (int g = 0; g < w.n_mb; ++g) {
-            hipLaunchKernelGGL(k_axpy_vol, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
-                               (const float *)(w.p + (int64_t)g * w.nv), w.nv, w.F, (const double *)(w.alpha + g * w.F));
+        for (int g = 0; g < w.n_mb; ++g)  // r -= alpha q (and |r|^2, max |r|)
             hipLaunchKernelGGL(k_axpy_res, dim3(gs), dim3(kVecThreads), 0, st, w.r + (int64_t)g * w.ns,
                                (const float *)(w.q + (int64_t)g * w.ns), w.ns, w.F, (const double *)(w.alpha + g * w.F),
-                               w.dotp + (int64_t)g * kVecBlocks * w.F);
-        }
+                               w.dotp + (int64_t)g * kVecBlocks * w.F, amax ? amax + (int64_t)g * w.F : nullptr);
         XCT_HIP_TRY(hipGetLastError());
         if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
         if ((rc = c.scalars(kSetResid, w.resid + (int64_t)(k + 1) * w.Bp))) return rc;
         if ((rc = c.product(1))) return rc;  // s = A^T r, gamma'
         if ((rc = c.scalars(kSetBeta, nullptr))) return rc;
-        for (int g = 0; g < w.n_mb; ++g) {
-            hipLaunchKernelGGL(k_xpby, dim3(gv), dim3(kVecThreads), 0, st, w.p + (int64_t)g * w.nv,
-                               (const float *)(w.s + (int64_t)g * w.nv), w.nv, w.F, (const double *)(w.beta + g * w.F));
-        }
+        for (int g = 0; g < w.n_mb; ++g)  // x += alpha p ; p = s + beta p (and max |p|)
+            hipLaunchKernelGGL(k_update_xp, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
+                               w.p + (int64_t)g * w.nv, (const float *)(w.s + (int64_t)g * w.nv), w.nv, w.F,
+                               (const double *)(w.alpha + g * w.F), (const double *)(w.beta + g * w.F),
+                               amax ? amax + (int64_t)g * w.F : nullptr);
         XCT_HIP_TRY(hipGetLastError());
     }
     for (int g = 0; g < w.n_mb; ++g) {
         rc = launch_from_internal(m->vol, w.x + (int64_t)g * w.nv, batch, g * w.F, w.F, x, XCT_F32, st);
         if (rc) return rc;
     }
-    if (resid || status) {
-        std::vector<double> rh((size_t)(iters + 1) * w.Bp);
-        std::vector<int32_t> sh(w.Bp);
-        XCT_HIP_TRY(hipMemcpyAsync(rh.data(), w.resid, sizeof(double) * rh.size(), hipMemcpyDeviceToHost, st));
-        XCT_HIP_TRY(hipMemcpyAsync(sh.data(), w.stopped, sizeof(int32_t) * sh.size(), hipMemcpyDeviceToHost, st));
-        XCT_HIP_TRY(hipStreamSynchronize(st));
-        if (resid)
-            for (int k = 0; k <= iters; ++k)
-                for (int b = 0; b < batch; ++b) resid[(int64_t)k * batch + b] = rh[(size_t)k * w.Bp + b];
-        if (status)
-            for (int b = 0; b < batch; ++b) status[b] = sh[b];
-    }
+    // the residual rows (padded batch Bp on the device) and the status words
+    // straight into the caller's arrays
+    if (resid)
+        XCT_HIP_TRY(hipMemcpy2DAsync(resid, sizeof(double) * batch, w.resid, sizeof(double) * w.Bp,
+                                     sizeof(double) * batch, iters + 1, hipMemcpyDeviceToHost, st));
+    if (status)
+        XCT_HIP_TRY(hipMemcpyAsync(status, w.stopped, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st));
+    if (resid || status) XCT_HIP_TRY(hipStreamSynchronize(st));
     return XCT_OK;
 }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,8 @@ constexpr int kTileSlots = 64;
 // ELL entries are stored in groups of kGroup consecutive steps per lane so
 // one lane reads a group with a single wide load.
 constexpr int kGroup = 4;
+// Most slices fused per matrix pass (32 with 16-bit operands, 16 with FP32).
+constexpr int kMaxFuse = 32;
 // One operator (A or A^T) in staged-ELL form.
 //
 // Output rows are grouped in tiles of 64 (one wavefront of lanes); W
@@ -91,6 +94,11 @@ struct xct_matrix {
     xct::Grid vol, sino;
     xct::OpPlan A, AT;
     double build_seconds = 0.0;
+    // The streamed calls' events, created at the first such call on the
+    // handle and released with it; the mutex serialises streamed calls that
+    // share the handle (each returns only once its streams are drained).
+    std::mutex stream_mu;
+    hipEvent_t stream_ev[7] = {};
 };
 
 namespace xct {
@@ -98,6 +106,11 @@ namespace xct {
 // thread-local last error
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
+
+// The library's device allocations (counted for xct_device_memory; see
+// build.hip for the failure injection).
+hipError_t dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
 
 #define XCT_HIP_TRY(expr)                                                                   \
     do {                                                                                    \

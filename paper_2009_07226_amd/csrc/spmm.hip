@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -298,6 +299,8 @@ template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
 // wavefront holds two FP32 accumulator sets of 16 slices (register budget).
 template <int FMT, int F, int RT> struct ReadBatch { static constexpr int value = 4; };
 template <> struct ReadBatch<XCT_F32, 16, 2> { static constexpr int value = 2; };
+template <> struct ReadBatch<XCT_F16, 32, 1> { static constexpr int value = 2; };
+template <> struct ReadBatch<XCT_BF16, 32, 1> { static constexpr int value = 2; };
 
 // RT: row tiles per wavefront (a.W / RT wavefronts per block); H16: FP16
 // arithmetic on an FP16 matrix (F >= 2).
@@ -712,6 +715,11 @@ static int launch_rt(const SpmmLaunch &L, hipStream_t st) {
         case 4: return launch_arith<FMT, 4, RT>(L, st);
         case 8: return launch_arith<FMT, 8, RT>(L, st);
         case 16: return launch_arith<FMT, 16, RT>(L, st);
+        case 32:
+            // 32 fused slices: 16-bit operands only (64-byte staged rows, as
+            // FP32 at 16) and one row tile per wavefront (32 accumulators)
+            if constexpr (FMT != XCT_F32 && RT == 1) return launch_arith<FMT, 32, RT>(L, st);
+            return fail(XCT_ERR_UNSUPPORTED, "32 fused slices need a 16-bit matrix and one row tile per wavefront");
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
 }
@@ -874,6 +882,12 @@ __global__ void k_absmax(const void *nat, int io, int64_t plane, int batch, int 
     }
 }
 
+// Clear the per-slice maxima before the first group (a kernel, not a memset
+// node, so that a caller may capture the call into a graph).
+__global__ void k_clear_amax(uint32_t *amax, int n) {
+    if ((int)threadIdx.x < n) amax[threadIdx.x] = 0u;
+}
+
 // m = 2^ceil(log2 max) (1 for a zero or non-finite max), scale = m, inv = 1/m.
 // amax is cleared after it is read so the next group can reuse it.
 __global__ void k_pow2_scale(uint32_t *amax, int F, float *scale, float *inv) {
@@ -917,6 +931,7 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
         case 4: hipLaunchKernelGGL(k_to_internal<4>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         case 8: hipLaunchKernelGGL(k_to_internal<8>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         case 16: hipLaunchKernelGGL(k_to_internal<16>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 32: hipLaunchKernelGGL(k_to_internal<32>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
     XCT_HIP_TRY(hipGetLastError());
@@ -934,6 +949,7 @@ int launch_from_internal(const Grid &g, const float *internal, int batch, int s0
         case 4: hipLaunchKernelGGL(k_from_internal<4>, grid, blk, 0, st, c, internal, nat); break;
         case 8: hipLaunchKernelGGL(k_from_internal<8>, grid, blk, 0, st, c, internal, nat); break;
         case 16: hipLaunchKernelGGL(k_from_internal<16>, grid, blk, 0, st, c, internal, nat); break;
+        case 32: hipLaunchKernelGGL(k_from_internal<32>, grid, blk, 0, st, c, internal, nat); break;
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
     XCT_HIP_TRY(hipGetLastError());
@@ -967,38 +983,43 @@ struct SpmmWs {
     float *scale, *inv;
 };
 
-static size_t spmm_ws_layout(const xct_matrix *m, int batch, char *base, SpmmWs *w) {
-    const int F = run_fuse(batch, m->fuse);
+// Workspace of one fused group of F slices: the staged operand in the
+// storage dtype, the FP32 sums, and the per-slice max, scale and inverse.
+static size_t spmm_ws_layout_f(const xct_matrix *m, int F, char *base, SpmmWs *w) {
     const int64_t tiles = std::max(m->vol.n_tiles, m->sino.n_tiles);
     const size_t in_b = align256((size_t)tiles * kTileSlots * F * elem_bytes(m->vdt));
     const size_t out_b = align256((size_t)tiles * kTileSlots * F * sizeof(float));
-    const size_t small = align256(sizeof(uint32_t) * 16) * 3;
+    const size_t small = align256(sizeof(uint32_t) * kMaxFuse) * 3;
     if (w) {
         w->in = base;
         w->out = (float *)(base + in_b);
         char *p = base + in_b + out_b;
         w->amax = (uint32_t *)p;
-        w->scale = (float *)(p + align256(sizeof(uint32_t) * 16));
-        w->inv = (float *)(p + 2 * align256(sizeof(uint32_t) * 16));
+        w->scale = (float *)(p + align256(sizeof(uint32_t) * kMaxFuse));
+        w->inv = (float *)(p + 2 * align256(sizeof(uint32_t) * kMaxFuse));
     }
     return in_b + out_b + small;
 }
 
-int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
-                     void *workspace, void *stream) {
-    if (!m || !src || !dst || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
-    if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
-    if (!valid_dtype(io)) return fail(XCT_ERR_INVALID, "bad io dtype");
-    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
-    hipStream_t st = (hipStream_t)stream;
+static size_t spmm_ws_layout(const xct_matrix *m, int batch, char *base, SpmmWs *w) {
+    return spmm_ws_layout_f(m, run_fuse(batch, m->fuse), base, w);
+}
+
+// The product of spmm_call with F slices fused per matrix pass (any power of
+// two up to the matrix's fuse: the plan's stages fit the LDS at any smaller
+// F) and a workspace of spmm_ws_layout_f(m, F) bytes.
+static int spmm_call_f(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
+                       void *workspace, int F, hipStream_t st) {
     const OpPlan &op = dir ? m->AT : m->A;
     const Grid &gin = dir ? m->sino : m->vol;
     const Grid &gout = dir ? m->vol : m->sino;
     SpmmWs w;
-    spmm_ws_layout(m, batch, (char *)workspace, &w);
-    const int F = run_fuse(batch, m->fuse);
+    spmm_ws_layout_f(m, F, (char *)workspace, &w);
     const bool norm = m->vdt != XCT_F32;
-    if (norm) XCT_HIP_TRY(hipMemsetAsync(w.amax, 0, sizeof(uint32_t) * 16, st));
+    if (norm) {
+        hipLaunchKernelGGL(k_clear_amax, dim3(1), dim3(64), 0, st, w.amax, kMaxFuse);
+        XCT_HIP_TRY(hipGetLastError());
+    }
     for (int s0 = 0; s0 < batch; s0 += F) {
         int rc;
         if (norm) {
@@ -1014,6 +1035,15 @@ int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batc
         if (rc) return rc;
     }
     return XCT_OK;
+}
+
+int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
+                     void *workspace, void *stream) {
+    if (!m || !src || !dst || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
+    if (!valid_dtype(io)) return fail(XCT_ERR_INVALID, "bad io dtype");
+    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
+    return spmm_call_f(m, dir, src, dst, batch, io, workspace, run_fuse(batch, m->fuse), (hipStream_t)stream);
 }
 
 size_t spmm_workspace(const xct_matrix *m, int batch) { return spmm_ws_layout(m, batch, nullptr, nullptr); }

@@ -33,14 +33,6 @@ static size_t stream_ws_layout(const xct_matrix *m, int dir, int chunk, xct_dtyp
     return 2 * in_b + 2 * out_b + spmm_workspace(m, chunk);
 }
 
-struct Events {
-    hipEvent_t e[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    ~Events() {
-        for (hipEvent_t x : e)
-            if (x) (void)hipEventDestroy(x);
-    }
-};
-
 static int streamed(const xct_matrix *m, int dir, const void *src_host, void *dst_host, int batch, int chunk,
                     xct_dtype io, void *workspace, void *compute, void *h2d, void *d2h) {
     if (!m || !src_host || !dst_host || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
@@ -63,45 +55,48 @@ static int streamed(const xct_matrix *m, int dir, const void *src_host, void *ds
         return rc == XCT_OK;
     };
     // per buffer slot: input copied in (0, 1), product done (2, 3), output
-    // copied out (4, 5); 6: the compute stream's earlier work
-    Events ev;
-    for (hipEvent_t &x : ev.e)
-        if (!chk(hipEventCreateWithFlags(&x, hipEventDisableTiming), "hipEventCreateWithFlags")) return rc;
+    // copied out (4, 5); 6: the compute stream's earlier work.  The handle
+    // keeps them from its first streamed call on.
+    std::lock_guard<std::mutex> lock(const_cast<xct_matrix *>(m)->stream_mu);
+    hipEvent_t *ev = const_cast<xct_matrix *>(m)->stream_ev;
+    for (int q = 0; q < 7; ++q)
+        if (!ev[q] && !chk(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "hipEventCreateWithFlags"))
+            return rc;
     // The workspace is ordered on the compute stream (its previous user may
     // still be running there): both copy streams start after that work.
-    if (!chk(hipEventRecord(ev.e[6], sc), "hipEventRecord") ||
-        !chk(hipStreamWaitEvent(si, ev.e[6], 0), "hipStreamWaitEvent") ||
-        !chk(hipStreamWaitEvent(so, ev.e[6], 0), "hipStreamWaitEvent"))
+    if (!chk(hipEventRecord(ev[6], sc), "hipEventRecord") ||
+        !chk(hipStreamWaitEvent(si, ev[6], 0), "hipStreamWaitEvent") ||
+        !chk(hipStreamWaitEvent(so, ev[6], 0), "hipStreamWaitEvent"))
         return rc;
     const int nc = (batch + chunk - 1) / chunk;
     auto slices = [&](int c) { return std::min(chunk, batch - c * chunk); };
     auto copy_in = [&](int c) -> bool {
         const int slot = c & 1;
         // the product of chunk c - 2 has finished reading this input buffer
-        if (c >= 2 && !chk(hipStreamWaitEvent(si, ev.e[2 + slot], 0), "hipStreamWaitEvent")) return false;
+        if (c >= 2 && !chk(hipStreamWaitEvent(si, ev[2 + slot], 0), "hipStreamWaitEvent")) return false;
         return chk(hipMemcpyAsync(w.in[slot], (const char *)src_host + (size_t)c * chunk * in_slice,
                                   (size_t)slices(c) * in_slice, hipMemcpyHostToDevice, si),
                    "hipMemcpyAsync") &&
-               chk(hipEventRecord(ev.e[slot], si), "hipEventRecord");
+               chk(hipEventRecord(ev[slot], si), "hipEventRecord");
     };
     copy_in(0);
     for (int c = 0; c < nc && rc == XCT_OK; ++c) {
         const int slot = c & 1;
         if (c + 1 < nc && !copy_in(c + 1)) break;
-        if (!chk(hipStreamWaitEvent(sc, ev.e[slot], 0), "hipStreamWaitEvent")) break;
+        if (!chk(hipStreamWaitEvent(sc, ev[slot], 0), "hipStreamWaitEvent")) break;
         // the copy-out of chunk c - 2 has finished reading this output buffer
-        if (c >= 2 && !chk(hipStreamWaitEvent(sc, ev.e[4 + slot], 0), "hipStreamWaitEvent")) break;
+        if (c >= 2 && !chk(hipStreamWaitEvent(sc, ev[4 + slot], 0), "hipStreamWaitEvent")) break;
         const int r = spmm_call(m, dir, w.in[slot], w.out[slot], slices(c), io, w.spmm, sc);
         if (r) {
             rc = r;
             break;
         }
-        if (!chk(hipEventRecord(ev.e[2 + slot], sc), "hipEventRecord") ||
-            !chk(hipStreamWaitEvent(so, ev.e[2 + slot], 0), "hipStreamWaitEvent") ||
+        if (!chk(hipEventRecord(ev[2 + slot], sc), "hipEventRecord") ||
+            !chk(hipStreamWaitEvent(so, ev[2 + slot], 0), "hipStreamWaitEvent") ||
             !chk(hipMemcpyAsync((char *)dst_host + (size_t)c * chunk * out_slice, w.out[slot],
                                 (size_t)slices(c) * out_slice, hipMemcpyDeviceToHost, so),
                  "hipMemcpyAsync") ||
-            !chk(hipEventRecord(ev.e[4 + slot], so), "hipEventRecord"))
+            !chk(hipEventRecord(ev[4 + slot], so), "hipEventRecord"))
             break;
     }
     // everything enqueued completes before the events are released

@@ -2,6 +2,8 @@
 // ceiling for the SpMM's matrix stream (not part of the method).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -12,14 +14,42 @@ namespace xct {
 
 // Streaming read of a buffer (16-byte non-temporal loads, grid-stride), the
 // reference ceiling for the SpMM's matrix stream.
-__global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n, uint32_t *sink) {
+static __device__ uint32_t g_probe_sink;  // target of the probe's (practically never taken) store
+
+__global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n) {
     uint32_t acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const u32x4 v = __builtin_nontemporal_load(p + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
-    if (acc == 0x9e3779b9u) sink[0] = acc;  // keeps the loads; practically never stores
+    if (acc == 0x9e3779b9u) g_probe_sink = acc;  // keeps the loads; practically never stores
 }
+
+// Number of elements of v that are NaN or infinite (dt: 0 FP32, 1 FP16,
+// 2 BF16), added into *count (cleared by k_zero_count first).
+__global__ void k_zero_count(unsigned long long *count) { *count = 0ull; }
+
+__global__ void __launch_bounds__(256) k_count_nonfinite(const void *v, int64_t n, int dt,
+                                                         unsigned long long *count) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool bad;
+        if (dt == XCT_F32) {
+            bad = (__float_as_uint(((const float *)v)[i]) & 0x7f800000u) == 0x7f800000u;
+        } else {
+            const uint16_t h = ((const uint16_t *)v)[i];
+            bad = dt == XCT_F16 ? (h & 0x7c00u) == 0x7c00u : (h & 0x7f80u) == 0x7f80u;
+        }
+        c += bad ? 1ull : 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+// The probe's two timing events, created once per device.
+constexpr int kMaxProbeDevices = 64;
+static hipEvent_t g_probe_ev[kMaxProbeDevices][2];
+static std::mutex g_probe_mu;
 }  // namespace xct
 
 using namespace xct;
@@ -28,30 +58,41 @@ extern "C" int xct_read_bandwidth(const void *buf, int64_t bytes, int reps, doub
     if (!buf || !gbps || bytes < 16 || reps < 1) return fail(XCT_ERR_INVALID, "bad argument");
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = bytes / 16;
-    uint32_t *sink = nullptr;
-    XCT_HIP_TRY(hipMalloc(&sink, sizeof(uint32_t)));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = XCT_OK;
-    hipError_t he = hipEventCreate(&e0);
-    if (he == hipSuccess) he = hipEventCreate(&e1);
+    int dev = -1;
+    XCT_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxProbeDevices) return fail(XCT_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_probe_mu);  // one probe at a time per process: its events are shared
+    hipEvent_t *ev = g_probe_ev[dev];
+    for (int q = 0; q < 2; ++q)
+        if (!ev[q]) XCT_HIP_TRY(hipEventCreate(&ev[q]));
     const int grid = 4096;
-    if (he == hipSuccess) {
-        hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n, sink);
-        he = hipEventRecord(e0, st);
+    hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n);  // warm-up
+    XCT_HIP_TRY(hipGetLastError());
+    XCT_HIP_TRY(hipEventRecord(ev[0], st));
+    for (int r = 0; r < reps; ++r) {
+        hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n);
+        XCT_HIP_TRY(hipGetLastError());
     }
-    for (int r = 0; r < reps && he == hipSuccess; ++r) {
-        hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n, sink);
-        he = hipGetLastError();
-    }
-    if (he == hipSuccess) he = hipEventRecord(e1, st);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    XCT_HIP_TRY(hipEventRecord(ev[1], st));
+    XCT_HIP_TRY(hipEventSynchronize(ev[1]));
     float ms = 0.f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-    if (he != hipSuccess) rc = fail(XCT_ERR_HIP, std::string("read probe: ") + hipGetErrorString(he));
-    else *gbps = (double)n * 16.0 * reps / (ms * 1e-3) / 1e9;
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(sink);
-    return rc;
+    XCT_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    *gbps = (double)n * 16.0 * reps / (ms * 1e-3) / 1e9;
+    return XCT_OK;
 }
 
+extern "C" int xct_count_nonfinite(const void *v, int64_t n, xct_dtype dt, int64_t *count, void *stream) {
+    if (!v || !count || n < 0) return fail(XCT_ERR_INVALID, "bad argument");
+    if (!valid_dtype(dt)) return fail(XCT_ERR_INVALID, "bad dtype");
+    if (((uintptr_t)count & 7) != 0) return fail(XCT_ERR_INVALID, "count must be 8-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *c = (unsigned long long *)count;
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, c);
+    XCT_HIP_TRY(hipGetLastError());
+    if (n > 0) {
+        const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(grid), dim3(256), 0, st, v, n, (int)dt, c);
+        XCT_HIP_TRY(hipGetLastError());
+    }
+    return XCT_OK;
+}

@@ -103,6 +103,10 @@ def lib():
     L.xct_pgrad_workspace_bytes.restype = sz
     L.xct_projected_gradient.argtypes = [vp, vp, vp, i, i, vp, ctypes.c_float, ctypes.c_float, i, vp, vp]
     L.xct_projected_gradient.restype = i
+    L.xct_count_nonfinite.argtypes = [vp, i64, i, vp, vp]
+    L.xct_count_nonfinite.restype = i
+    L.xct_device_memory.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.xct_device_memory.restype = i
     L.xct_last_error.argtypes = []
     L.xct_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -141,6 +145,20 @@ def _require(t: torch.Tensor, shape, name: str, dtype=None):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _require_workspace(ws: torch.Tensor, nbytes: int, device: torch.device):
+    """A caller-supplied workspace must be a contiguous device tensor of at
+    least ``nbytes`` bytes on the matrix's device (the C ABI takes no size)."""
+    if not isinstance(ws, torch.Tensor):
+        raise TypeError("workspace must be a torch.Tensor")
+    if ws.device != device:
+        raise ValueError(f"workspace must be on {device}, got {ws.device}")
+    if not ws.is_contiguous():
+        raise ValueError("workspace must be contiguous")
+    have = ws.numel() * ws.element_size()
+    if have < nbytes:
+        raise ValueError(f"workspace holds {have} bytes, the call needs {nbytes}")
 
 
 class Matrix:
@@ -216,30 +234,40 @@ class Matrix:
 
 
 def project(A: Matrix, x: torch.Tensor, out: Optional[torch.Tensor] = None,
-            workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """y = A x for a batch x of shape (B, n, n); returns (B, n_angles, n_channels) in x's dtype."""
+            workspace: Optional[torch.Tensor] = None, check_finite: bool = False) -> torch.Tensor:
+    """y = A x for a batch x of shape (B, n, n); returns (B, n_angles, n_channels) in x's dtype.
+    With ``check_finite``, raise ValueError if x holds a NaN or an infinity."""
     B = x.shape[0] if x.dim() == 3 else -1
     _require(x, (B,) + A.vol_shape, "x")
+    if check_finite and count_nonfinite(x):
+        raise ValueError("x holds non-finite values")
     if out is None:
         out = torch.empty((B,) + A.sino_shape, dtype=x.dtype, device=x.device)
     _require(out, (B,) + A.sino_shape, "out", x.dtype)
     if workspace is None:
         workspace = A.spmm_workspace(B)
+    else:
+        _require_workspace(workspace, lib().xct_spmm_workspace_bytes(A.handle, B), A.device)
     _check(lib().xct_project(A.handle, x.data_ptr(), out.data_ptr(), B, _dt(x.dtype), workspace.data_ptr(),
                              _stream()))
     return out
 
 
 def backproject(A: Matrix, y: torch.Tensor, out: Optional[torch.Tensor] = None,
-                workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """x = A^T y for a batch y of shape (B, n_angles, n_channels); returns (B, n, n)."""
+                workspace: Optional[torch.Tensor] = None, check_finite: bool = False) -> torch.Tensor:
+    """x = A^T y for a batch y of shape (B, n_angles, n_channels); returns (B, n, n).
+    With ``check_finite``, raise ValueError if y holds a NaN or an infinity."""
     B = y.shape[0] if y.dim() == 3 else -1
     _require(y, (B,) + A.sino_shape, "y")
+    if check_finite and count_nonfinite(y):
+        raise ValueError("y holds non-finite values")
     if out is None:
         out = torch.empty((B,) + A.vol_shape, dtype=y.dtype, device=y.device)
     _require(out, (B,) + A.vol_shape, "out", y.dtype)
     if workspace is None:
         workspace = A.spmm_workspace(B)
+    else:
+        _require_workspace(workspace, lib().xct_spmm_workspace_bytes(A.handle, B), A.device)
     _check(lib().xct_backproject(A.handle, y.data_ptr(), out.data_ptr(), B, _dt(y.dtype), workspace.data_ptr(),
                                  _stream()))
     return out
@@ -279,9 +307,11 @@ def _streamed(which: int, A: Matrix, src: torch.Tensor, out: Optional[torch.Tens
         out = torch.empty((B,) + out_shape, dtype=src.dtype, pin_memory=True)
     _require_host(out, (B,) + out_shape, "out", src.dtype)
     chunk = int(chunk) if chunk else 16
+    nb = lib().xct_stream_workspace_bytes(A.handle, which, chunk, _dt(src.dtype))
     if workspace is None:
-        nb = lib().xct_stream_workspace_bytes(A.handle, which, chunk, _dt(src.dtype))
         workspace = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    else:
+        _require_workspace(workspace, nb, A.device)
     h2d, d2h = _copy_streams(A.device)
     fn = lib().xct_project_streamed if which == 0 else lib().xct_backproject_streamed
     _check(fn(A.handle, src.data_ptr(), out.data_ptr(), B, chunk, _dt(src.dtype), workspace.data_ptr(),
@@ -314,6 +344,8 @@ def cgls(A: Matrix, y: torch.Tensor, iters: int, out: Optional[torch.Tensor] = N
     _require(out, (B,) + A.vol_shape, "out", torch.float32)
     if workspace is None:
         workspace = A.cgls_workspace(B, iters)
+    else:
+        _require_workspace(workspace, lib().xct_cgls_workspace_bytes(A.handle, B, int(iters)), A.device)
     resid = np.empty((iters + 1, B), np.float64) if want_resid else None
     status = np.empty(B, np.int32) if want_resid else None
     _check(lib().xct_cgls(A.handle, y.data_ptr(), _dt(y.dtype), out.data_ptr(), B, int(iters),
@@ -348,11 +380,30 @@ def projected_gradient(A: Matrix, y: torch.Tensor, iters: int, step, lam: float 
             raise ValueError(f"step has {tau.numel()} entries, expected {B}")
     else:
         tau = torch.full((B,), float(step), dtype=torch.float32, device=y.device)
+    nb = lib().xct_pgrad_workspace_bytes(A.handle, B)
     if workspace is None:
-        workspace = torch.empty(lib().xct_pgrad_workspace_bytes(A.handle, B), dtype=torch.uint8, device=y.device)
+        workspace = torch.empty(nb, dtype=torch.uint8, device=y.device)
+    else:
+        _require_workspace(workspace, nb, A.device)
     _check(lib().xct_projected_gradient(A.handle, y.data_ptr(), out.data_ptr(), B, int(iters), tau.data_ptr(),
                                         float(lam), float(eps), 1 if nonneg else 0, workspace.data_ptr(), _stream()))
     return out
+
+
+def count_nonfinite(t: torch.Tensor) -> int:
+    """Number of NaN / infinite elements of a contiguous device tensor
+    (FP32, FP16 or BF16); waits for the count."""
+    _require(t, tuple(t.shape), "tensor")
+    c = torch.empty((), dtype=torch.int64, device=t.device)
+    _check(lib().xct_count_nonfinite(t.data_ptr(), t.numel(), _dt(t.dtype), c.data_ptr(), _stream()))
+    return int(c.item())
+
+
+def device_memory() -> dict:
+    """Device buffers (count and bytes) the library holds for its matrices."""
+    n, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().xct_device_memory(ctypes.byref(n), ctypes.byref(b)))
+    return {"buffers": n.value, "bytes": b.value}
 
 
 def profile_enable(on: bool = True) -> None:

@@ -1,0 +1,104 @@
+"""Failure handling of the library on the GPU, forced from the host (no
+kernel faults): allocation failures at every allocation of a build (by
+injection) and a request beyond the device's memory return XCT_ERR_OOM and
+release everything taken; non-finite inputs are counted, refused on request,
+and in CGLS confined to their slice with status 2."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+xct = pytest.importorskip("paper_2009_07226_amd")
+from paper_2009_07226_amd import phantoms  # noqa: E402
+
+
+def banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def test_injected_allocation_failures_release_everything():
+    base = xct.device_memory()
+    failures = 0
+    try:
+        for n in range(1, 200):
+            os.environ["XCT_FAULT_ALLOC"] = str(n)
+            try:
+                A = xct.Matrix(37, 23, 41, "f16")
+            except xct.XctError as e:
+                assert e.code == -2, e
+                assert xct.device_memory() == base, (n, xct.device_memory(), base)
+                failures += 1
+                continue
+            # the n-th allocation is past the build's last one: it succeeded
+            held = xct.device_memory()
+            assert held["buffers"] > base["buffers"]
+            A.free()
+            break
+        else:
+            pytest.fail("the build never completed")
+    finally:
+        os.environ.pop("XCT_FAULT_ALLOC", None)
+    banner(f"{failures} allocation sites failed in turn, each released everything")
+    assert failures >= 10
+    assert xct.device_memory() == base
+
+
+def test_request_beyond_device_memory_is_oom():
+    # 4096^2 voxels x 3000 angles with FP32 values: about 6e10 entries, some
+    # 400 GB for A alone, beyond the device's 288 GB
+    base = xct.device_memory()
+    with pytest.raises(xct.XctError) as e:
+        xct.Matrix(4096, 3000, 4096, "f32")
+    assert e.value.code == -2
+    banner(f"oversized request: {e.value}")
+    assert xct.device_memory() == base
+    # the device is still usable afterwards
+    A = xct.Matrix(16, 12, 16, "f32")
+    y = xct.project(A, torch.ones((1, 16, 16), device="cuda"))
+    assert bool(torch.isfinite(y).all())
+    A.free()
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16, torch.bfloat16])
+def test_count_nonfinite_and_checked_products(dt):
+    x = torch.rand((3, 37, 37), device="cuda").to(dt)
+    assert xct.count_nonfinite(x) == 0
+    x[0, 1, 2] = float("nan")
+    x[2, 5, 5] = float("inf")
+    x[2, 6, 6] = float("-inf")
+    assert xct.count_nonfinite(x) == 3 == int((~torch.isfinite(x.float())).sum())
+    A = xct.Matrix(37, 23, 41, "f32")
+    with pytest.raises(ValueError):
+        xct.project(A, x, check_finite=True)
+    y = torch.rand((3, 23, 41), device="cuda").to(dt)
+    xct.backproject(A, y, check_finite=True)
+    y[1, 0, 0] = float("nan")
+    with pytest.raises(ValueError):
+        xct.backproject(A, y, check_finite=True)
+    A.free()
+
+
+@pytest.mark.parametrize("vdt", ["f32", "f16"])
+def test_cgls_nonfinite_slice_is_reported_and_isolated(vdt):
+    N, M, C, B = 37, 23, 41, 4
+    A = xct.Matrix(N, M, C, vdt)
+    x_true = phantoms.ellipse_batch(N, B, 5, seed=9).cuda().float()
+    y = xct.project(A, x_true)
+    xg, rg, sg = xct.cgls(A, y, 6)
+    bad = y.clone()
+    bad[1, 3, 4] = float("nan")
+    bad[2, 0, 7] = float("inf")
+    xb, rb, sb = xct.cgls(A, bad, 6)
+    assert list(sb) == [0, 2, 2, 0]
+    assert float(xb[1].abs().max()) == 0.0 and float(xb[2].abs().max()) == 0.0
+    assert np.all(np.isnan(rb[:, 1])) and np.all(np.isnan(rb[:, 2]))
+    # the finite slices are solved exactly as without their neighbours' defects
+    for b in (0, 3):
+        assert torch.equal(xb[b], xg[b])
+        assert np.array_equal(rb[:, b], rg[:, b])
+    assert all(math.isfinite(v) for v in rb[:, 0])
+    A.free()

@@ -52,3 +52,25 @@ def test_argument_errors_without_device():
     g = ctypes.c_double()
     assert L.xct_read_bandwidth(None, 1 << 20, 1, ctypes.byref(g), None) == -1
     assert L.xct_profile_read(None, None) == -1
+    assert L.xct_count_nonfinite(None, 4, 0, None, None) == -1
+    assert L.xct_device_memory(None, None) == -1
+    # no matrix built in this process: the library holds no device memory
+    assert xct.device_memory() == {"buffers": 0, "bytes": 0}
+
+
+def test_workspace_checks_in_the_binding():
+    # a caller-supplied workspace is checked before the C ABI (which takes no
+    # size) could write past it: device, contiguity and byte count
+    import torch
+    from paper_2009_07226_amd import xct as binding
+    dev = torch.device("cpu")
+    binding._require_workspace(torch.empty(64, dtype=torch.uint8), 64, dev)
+    binding._require_workspace(torch.empty(16, dtype=torch.float32), 64, dev)  # 64 bytes
+    with pytest.raises(ValueError, match="needs 65"):
+        binding._require_workspace(torch.empty(64, dtype=torch.uint8), 65, dev)
+    with pytest.raises(ValueError, match="must be on"):
+        binding._require_workspace(torch.empty(64, dtype=torch.uint8), 1, torch.device("cuda", 0))
+    with pytest.raises(ValueError, match="contiguous"):
+        binding._require_workspace(torch.empty(8, 8, dtype=torch.uint8).t(), 1, dev)
+    with pytest.raises(TypeError):
+        binding._require_workspace(bytearray(64), 1, dev)
