@@ -71,7 +71,10 @@ hipError_t dev_alloc(void **p, size_t bytes) {
         return hipErrorOutOfMemory;
     }
     const hipError_t e = hipMalloc(p, bytes);
-    if (e == hipSuccess) g_alloc_live[*p] = bytes;
+    if (e == hipSuccess)
+        g_alloc_live[*p] = bytes;
+    else
+        (void)hipGetLastError();  // the failure is returned here; later calls must not see it again
     return e;
 }
 

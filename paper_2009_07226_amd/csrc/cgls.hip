@@ -226,7 +226,9 @@ __global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, do
         case kSetAlpha: {
             delta[b] = v;
             const double g = gamma[b];
-            if (stopped[b] || g == 0.0 || v == 0.0) {
+            if (stopped[b]) {
+                alpha[b] = 0.0;  // keeps its status (1 or 2)
+            } else if (g == 0.0 || v == 0.0) {
                 stopped[b] = 1;
                 alpha[b] = 0.0;
             } else {
