@@ -170,6 +170,25 @@ int xct_project(const xct_matrix *A, const void *x, void *y, int batch, xct_dtyp
 int xct_backproject(const xct_matrix *A, const void *y, void *x, int batch, xct_dtype io,
                     void *workspace, void *stream);
 
+/*
+ * Allocation-free projection (which = 0: out = A in) or backprojection
+ * (which = 1: out = A^T in), for callers that cannot allocate device memory
+ * (code under graph capture, serving loops, harnesses that forbid it).
+ * Same arguments and results as xct_project / xct_backproject, without the
+ * workspace: the staging buffers are a fixed array of
+ * xct_noalloc_scratch_bytes() (64 MiB) of device memory that the library
+ * holds on every GPU it runs on until the process ends; the call itself
+ * allocates nothing.  Slices are fused per matrix pass as far as that array
+ * holds them; a geometry whose single slice needs more staging returns
+ * XCT_ERR_UNSUPPORTED.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap in time on one GPU (other streams or threads) race
+ * and must be serialised by the caller.  Errors: XCT_ERR_INVALID,
+ * XCT_ERR_UNSUPPORTED, XCT_ERR_HIP.
+ */
+int xct_apply_noalloc(const xct_matrix *A, int which, const void *in, void *out, int batch, xct_dtype io,
+                      void *stream);
+size_t xct_noalloc_scratch_bytes(void);
+
 /* Device workspace needed by xct_project_streamed (which = 0) or
  * xct_backproject_streamed (which = 1) for chunks of `chunk` slices of dtype `io`. */
 size_t xct_stream_workspace_bytes(const xct_matrix *A, int which, int chunk, xct_dtype io);

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1046,6 +1047,38 @@ int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batc
     return spmm_call_f(m, dir, src, dst, batch, io, workspace, run_fuse(batch, m->fuse), (hipStream_t)stream);
 }
 
+// ---- the allocation-free form of the products --------------------------------
+//
+// For callers that cannot allocate device memory (graph capture, serving
+// loops): the staging workspace is a fixed array of device memory that the
+// code object carries, one copy per GPU, held until the process ends.  Its
+// device address is looked up once per device (a host-side reference to the
+// array names no device memory).  Every call on a GPU uses that GPU's one
+// array: calls that overlap on one GPU race, whatever their streams.  The
+// array's leftovers from an earlier call are harmless: the conversion writes
+// every staged element and the product every sum before they are read, and
+// the per-slice maxima are cleared first.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_for_current_device(void **out) {
+    int dev = -1;
+    XCT_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(XCT_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        XCT_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(XCT_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return XCT_OK;
+}
+
 size_t spmm_workspace(const xct_matrix *m, int batch) { return spmm_ws_layout(m, batch, nullptr, nullptr); }
 
 }  // namespace xct
@@ -1065,6 +1098,29 @@ extern "C" int xct_project(const xct_matrix *m, const void *x, void *y, int batc
 extern "C" int xct_backproject(const xct_matrix *m, const void *y, void *x, int batch, xct_dtype io, void *workspace,
                                void *stream) {
     return spmm_call(m, 1, y, x, batch, io, workspace, stream);
+}
+
+extern "C" size_t xct_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int xct_apply_noalloc(const xct_matrix *m, int which, const void *in, void *out, int batch,
+                                 xct_dtype io, void *stream) {
+    if (!m || !in || !out) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (which != 0 && which != 1) return fail(XCT_ERR_INVALID, "which must be 0 (A x) or 1 (A^T y)");
+    if (batch < 1) return fail(XCT_ERR_INVALID, "batch must be >= 1");
+    if (!valid_dtype(io)) return fail(XCT_ERR_INVALID, "bad io dtype");
+    // the most slices per matrix pass whose staging fits the array
+    int F = run_fuse(batch, m->fuse);
+    while (F > 1 && spmm_ws_layout_f(m, F, nullptr, nullptr) > kScratchBytes) F >>= 1;
+    const size_t need = spmm_ws_layout_f(m, F, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(XCT_ERR_UNSUPPORTED, "one slice of this geometry needs " + std::to_string(need) +
+                                             " bytes of staging, beyond the " + std::to_string(kScratchBytes) +
+                                             "-byte allocation-free scratch; use xct_project / xct_backproject "
+                                             "with a workspace");
+    void *ws = nullptr;
+    int rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    return spmm_call_f(m, which, in, out, batch, io, ws, F, (hipStream_t)stream);
 }
 
 extern "C" int xct_profile_enable(int on) {
