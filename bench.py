@@ -43,8 +43,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "fwd+back projection GB/s & % HBM peak; CGLS s/iter, FP16-store vs FP32"
-BYTES_A = {"f32": 6, "f16": 4, "bf16": 4}    # stored bytes per matrix entry
-BYTES_X = {"f32": 4, "f16": 2, "bf16": 2}    # staged operand bytes per element
+BYTES_A = {"f32": 6, "f16": 4, "bf16": 4, "f64": 10}  # stored bytes per matrix entry
+BYTES_X = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}   # staged operand bytes per element
+BYTES_Y = {"f32": 4, "f16": 4, "bf16": 4, "f64": 8}   # sums written per output element
 
 
 def log(msg):
@@ -79,7 +80,7 @@ def time_products(xct, torch, A, x, steps, warmup=2):
     and, from the library's launch events, the SpMM kernel's launch times and
     its algorithmic byte rate (matrix entries + staged operand in + FP32 out)."""
     info = A.info()
-    dt = {0: "f32", 1: "f16", 2: "bf16"}[info["value_dtype"]]
+    dt = {0: "f32", 1: "f16", 2: "bf16", 3: "f64"}[info["value_dtype"]]
     B, N, M, C = x.shape[0], A.n, A.n_angles, A.n_channels
     F = min(int(info["fuse"]), 1 << max(0, (B - 1).bit_length()))
     y = torch.empty((B, M, C), dtype=x.dtype, device=x.device)
@@ -102,12 +103,13 @@ def time_products(xct, torch, A, x, steps, warmup=2):
     xct.profile_enable(False)
     prof = xct.profile_read()
     ms = e0.elapsed_time(e1) / steps
-    b_a, b_x = BYTES_A[dt], BYTES_X[dt]
+    b_a, b_x, b_y = BYTES_A[dt], BYTES_X[dt], BYTES_Y[dt]
     nnzA, nnzT = info["A"]["nnz"], info["AT"]["nnz"]
-    kb = {"A": nnzA * b_a + F * (N * N * b_x + M * C * 4), "AT": nnzT * b_a + F * (M * C * b_x + N * N * 4)}
+    kb = {"A": nnzA * b_a + F * (N * N * b_x + M * C * b_y), "AT": nnzT * b_a + F * (M * C * b_x + N * N * b_y)}
     (nA, msA), (nT, msT) = prof["A"], prof["AT"]
     ach = (kb["A"] * nA + kb["AT"] * nT) / ((msA + msT) * 1e-3) / 1e9
-    step_bytes = alg_bytes(nnzA, N * N, M * C, B, F, b_a) + alg_bytes(nnzT, M * C, N * N, B, F, b_a)
+    b_io = x.element_size()
+    step_bytes = alg_bytes(nnzA, N * N, M * C, B, F, b_a, b_io) + alg_bytes(nnzT, M * C, N * N, B, F, b_a, b_io)
     del y, xb, ws
     return {"dtype": dt, "fuse": F, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall / steps * 1e3, 4),
             "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 2), "bytes_step": step_bytes,
@@ -331,10 +333,13 @@ def main():
                          "fuse slices, PCIe-inclusive)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference for profiler byte counters)")
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"],
-                    help="matrix/operand storage of the timed projection step (FP32 is the headline path)")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16", "f64"],
+                    help="matrix/operand storage of the timed projection step (FP32 is the headline path; "
+                         "f64 times FP64 slices, without CGLS)")
     args = ap.parse_args()
 
+    if args.dtype == "f64":  # the FP64 variant: products only (CGLS runs on FP32 / 16-bit matrices)
+        args.no_cgls = args.no_large = True
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -368,7 +373,8 @@ def main():
     log(f"built in {info['build_seconds']:.2f} s: A nnz {info['A']['nnz']:,} padded {info['A']['padded']:,}; "
         f"A^T padded {info['AT']['padded']:,}")
     nnz = info["A"]["nnz"]
-    x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device=dev).float()
+    x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device=dev)
+    x = x.double() if args.dtype == "f64" else x.float()
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20

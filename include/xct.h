@@ -56,7 +56,7 @@ extern "C" {
 
 typedef struct xct_matrix xct_matrix; /* opaque; owns the device copies of A and A^T */
 
-typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2 } xct_dtype;
+typedef enum { XCT_F32 = 0, XCT_F16 = 1, XCT_BF16 = 2, XCT_F64 = 3 } xct_dtype;
 
 enum {
     XCT_OK = 0,
@@ -72,7 +72,8 @@ typedef struct {
     int tile_waves; /* row tiles (64 rows each) per workgroup: 1..16 (one wavefront each) or 32
                        (16 wavefronts holding two row tiles each); default 16 */
     int fuse;       /* largest number of slices fused per matrix pass (F); 1, 2, 4, 8, 16 or 32
-                       (32: F16/BF16 matrices with tile_waves <= 16 only); default 16 */
+                       (32: F16/BF16 matrices with tile_waves <= 16 only; FP64 matrices at most 8);
+                       default 16 (8 for FP64) */
     int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input
                        (T = lds_bytes / (64 * F * element size) input tiles, at most 1024);
                        default: all of the device's LDS per workgroup (160 KiB on gfx950) */
@@ -127,8 +128,11 @@ typedef struct {
  *   n_channels  detector channels, >= 1
  *   value_dtype storage of matrix values and of the staged kernel operand:
  *               XCT_F32 (16-bit stage-local index + FP32 value, 6 B per
- *               entry) or XCT_F16 / XCT_BF16 (index and value packed in
- *               4 B, Sec. III-C "data packing"); lengths are computed in
+ *               entry), XCT_F16 / XCT_BF16 (index and value packed in
+ *               4 B, Sec. III-C "data packing"), or XCT_F64 (index + FP64
+ *               value, 10 B per entry, FP64 operand and sums: the
+ *               double-precision variant of Sec. IV; at most 8 fused
+ *               slices, and not for xct_cgls); lengths are computed in
  *               FP64 and rounded to nearest-even once.
  *   opts        nullable; see xct_build_opts
  *   stream      stream for the build kernels; the call returns after they finish
@@ -155,7 +159,8 @@ size_t xct_spmm_workspace_bytes(const xct_matrix *A, int batch);
  * pass per group of up to `fuse` slices).
  *   x         device, [batch][n][n] of dtype `io`
  *   y         device, [batch][n_angles][n_channels] of dtype `io` (written)
- *   io        dtype of x and y.  With an F16/BF16 matrix the operand is
+ *   io        dtype of x and y (any xct_dtype; an FP64 matrix keeps FP64
+ *             io exact, and rounds narrower io once).  With an F16/BF16 matrix the operand is
  *             scaled per slice by a power of two no smaller than its
  *             max-norm before it is rounded to 16 bits, and the FP32 sums
  *             are scaled back (Sec. III-C "adaptive normalization").

@@ -414,8 +414,8 @@ __global__ void k_plan(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
 
 template <class Rows, int FMT>
 __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nwords, int W, int T, int SW,
-                       const int32_t *blk_stage, const int64_t *slab, uint16_t *slot, float *val, uint32_t *packed,
-                       int *err) {
+                       const int32_t *blk_stage, const int64_t *slab, uint16_t *slot, float *val, double *val64,
+                       uint32_t *packed, int *err) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x, P = nthr >> 6, R = W / P, wave = tid >> 6, lane = tid & 63;
     const int NV = W * kTileSlots;
@@ -454,6 +454,10 @@ __global__ void k_fill(Rows rows, StageOrder ord, int64_t n_row_tiles, int nword
                     const int64_t li = (int64_t)lane * kGroup + (n % kGroup);
                     slot[g * 768 + li] = (uint16_t)s;
                     val[g * 384 + 128 + li] = (float)len;
+                } else if (FMT == XCT_F64) {
+                    const int64_t li = (int64_t)lane * kGroup + (n % kGroup);
+                    slot[g * 1280 + li] = (uint16_t)s;
+                    val64[g * 320 + 64 + li] = len;
                 } else if (FMT == XCT_F16) {
                     packed[idx] = (s << 16) | dbl_to_half_bits(len);
                 } else {
@@ -490,14 +494,19 @@ __device__ __forceinline__ int phase_quad(int p, int a) {
 }
 
 // LDS bytes per step of a slab and fixed part, for a launch of k_balance.
-inline size_t balance_lds_step(xct_dtype vdt) { return (size_t)kTileSlots * (vdt == XCT_F32 ? 10 : 8); }
+inline size_t balance_lds_step(xct_dtype vdt) {
+    return (size_t)kTileSlots * (vdt == XCT_F64 ? 14 : vdt == XCT_F32 ? 10 : 8);
+}
 inline size_t balance_lds_fixed(int Q) { return (size_t)2 * kTileSlots * Q * sizeof(uint16_t); }
 
 template <int FMT, int Q>
 __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32_t *ids, int L_cap, uint16_t *slot,
-                                                float *val, uint32_t *packed, unsigned long long *n_done, int *err) {
+                                                float *val, double *val64, uint32_t *packed,
+                                                unsigned long long *n_done, int *err) {
     constexpr int CH = 16 / Q;  // chunks per staged row
     constexpr int NU = 64 / Q;  // units per wavefront
+    constexpr bool kSplit = FMT == XCT_F32 || FMT == XCT_F64;  // slots and lengths stored apart
+    typedef typename std::conditional<FMT == XCT_F64, uint64_t, uint32_t>::type EntT;
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x;
     const int64_t sid = ids[blockIdx.x];
@@ -505,10 +514,10 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
     const int L = (int)(slab[sid + 1] - g0) * kGroup;
     if (L == 0 || L > L_cap) return;  // whole workgroup (the host sorts slabs by length)
     char *p = smem;
-    uint32_t *ent = (uint32_t *)p;  // F32: length bits; 16-bit: packed entry
-    p += sizeof(uint32_t) * (size_t)L * 64;
-    uint16_t *eslot = (uint16_t *)p;  // F32 only
-    if (FMT == XCT_F32) p += sizeof(uint16_t) * (size_t)L * 64;
+    EntT *ent = (EntT *)p;  // F32 / F64: length bits; 16-bit: packed entry
+    p += sizeof(EntT) * (size_t)L * 64;
+    uint16_t *eslot = (uint16_t *)p;  // F32 / F64 only
+    if (kSplit) p += sizeof(uint16_t) * (size_t)L * 64;
     uint16_t *order = (uint16_t *)p;  // per lane: its steps sorted by row class
     p += sizeof(uint16_t) * (size_t)L * 64;
     uint16_t *src = (uint16_t *)p;  // new step -> old step, or 0x8000 | class for padding
@@ -527,6 +536,14 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
                 ent[(t + q) * 64 + lane] = __float_as_uint(vp[q]);
                 eslot[(t + q) * 64 + lane] = sp[q];
             }
+        } else if constexpr (FMT == XCT_F64) {
+            const uint16_t *sp = slot + g * 1280 + lane * kGroup;
+            const double *vp = val64 + g * 320 + 64 + lane * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                ent[(t + q) * 64 + lane] = (EntT)__double_as_longlong(vp[q]);
+                eslot[(t + q) * 64 + lane] = sp[q];
+            }
         } else {
             const uint32_t *pp = packed + (g * kTileSlots + lane) * kGroup;
 #pragma unroll
@@ -534,8 +551,8 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
         }
     }
     auto real_cls = [&](int t, int l, int &cls) -> bool {
-        const uint32_t e = ent[t * 64 + l];
-        if constexpr (FMT == XCT_F32) {
+        const EntT e = ent[t * 64 + l];
+        if constexpr (kSplit) {
             cls = eslot[t * 64 + l] & (Q - 1);
             return e != 0u;
         } else {
@@ -689,17 +706,17 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
 
     for (int t = 0; t < L; t += kGroup) {
         const int64_t g = g0 + t / kGroup;
-        uint32_t e[kGroup];
+        EntT e[kGroup];
         uint16_t sl[kGroup];
 #pragma unroll
         for (int q = 0; q < kGroup; ++q) {
             const int sidx = src[(t + q) * 64 + lane];
             if (sidx & 0x8000) {
-                e[q] = FMT == XCT_F32 ? 0u : (uint32_t)(sidx & 0xff) << 16;
+                e[q] = kSplit ? (EntT)0 : (EntT)(sidx & 0xff) << 16;
                 sl[q] = (uint16_t)(sidx & 0xff);
             } else {
                 e[q] = ent[sidx * 64 + lane];
-                sl[q] = FMT == XCT_F32 ? eslot[sidx * 64 + lane] : 0;
+                sl[q] = kSplit ? eslot[sidx * 64 + lane] : 0;
             }
         }
         if constexpr (FMT == XCT_F32) {
@@ -708,12 +725,20 @@ __global__ void __launch_bounds__(64) k_balance(const int64_t *slab, const int32
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 sp[q] = sl[q];
-                vp[q] = __uint_as_float(e[q]);
+                vp[q] = __uint_as_float((uint32_t)e[q]);
+            }
+        } else if constexpr (FMT == XCT_F64) {
+            uint16_t *sp = slot + g * 1280 + lane * kGroup;
+            double *vp = val64 + g * 320 + 64 + lane * kGroup;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                sp[q] = sl[q];
+                vp[q] = __longlong_as_double((long long)e[q]);
             }
         } else {
             uint32_t *pp = packed + (g * kTileSlots + lane) * kGroup;
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) pp[q] = e[q];
+            for (int q = 0; q < kGroup; ++q) pp[q] = (uint32_t)e[q];
         }
     }
     if (lane == 0) atomicAdd(n_done, 1ull);
@@ -956,12 +981,15 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
     if (rc) return rc;
     // at least one group: the kernel's prefetch may re-read group 0
     const size_t nent = (size_t)std::max<int64_t>(1, op.n_groups) * kTileSlots * kGroup;
-    const size_t ent_bytes = nent * (vdt == XCT_F32 ? 6 : 4);
+    const size_t ent_bytes = nent * entry_bytes(vdt);
     XCT_HIP_TRY(dev_alloc(&op.ent, ent_bytes));
     XCT_HIP_TRY(hipMemsetAsync(op.ent, 0, ent_bytes, st));
     if (vdt == XCT_F32) {
         op.slot = (uint16_t *)op.ent;
         op.val = (float *)op.ent;
+    } else if (vdt == XCT_F64) {
+        op.slot = (uint16_t *)op.ent;
+        op.val64 = (double *)op.ent;
     } else {
         op.packed = (uint32_t *)op.ent;
     }
@@ -969,12 +997,14 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
         XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)smem_win));
         hipLaunchKernelGGL(kern, dim3(nb), dim3(nthr), smem_win, st, rows, ord, n_row_tiles, nwords, W, T, SW,
-                           op.blk_stage, op.slab, op.slot, op.val, op.packed, (int *)d_err.p);
+                           op.blk_stage, op.slab, op.slot, op.val, op.val64, op.packed, (int *)d_err.p);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
     };
     if (vdt == XCT_F32)
         rc = fill(k_fill<Rows, XCT_F32>);
+    else if (vdt == XCT_F64)
+        rc = fill(k_fill<Rows, XCT_F64>);
     else if (vdt == XCT_F16)
         rc = fill(k_fill<Rows, XCT_F16>);
     else
@@ -1023,13 +1053,15 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
                 XCT_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                 (int)smem_b));
                 hipLaunchKernelGGL(kern, dim3((unsigned)ids[k].size()), dim3(64), smem_b, st, op.slab,
-                                   (const int32_t *)d_ids[k].p, (int)bc, op.slot, op.val, op.packed,
+                                   (const int32_t *)d_ids[k].p, (int)bc, op.slot, op.val, op.val64, op.packed,
                                    (unsigned long long *)d_done.p, (int *)d_err.p);
                 XCT_HIP_TRY(hipGetLastError());
                 return XCT_OK;
             };
             if (vdt == XCT_F32)
                 rc = Q == 4 ? bal(k_balance<XCT_F32, 4>) : bal(k_balance<XCT_F32, 8>);
+            else if (vdt == XCT_F64)
+                rc = Q == 4 ? bal(k_balance<XCT_F64, 4>) : bal(k_balance<XCT_F64, 8>);
             else if (vdt == XCT_F16)
                 rc = Q == 4 ? bal(k_balance<XCT_F16, 4>) : bal(k_balance<XCT_F16, 8>);
             else
@@ -1043,7 +1075,7 @@ static int build_op(OpPlan &op, const Rows &rows, const StageOrder &ord, int64_t
         if (err) return fail(XCT_ERR_INTERNAL, "slab reordering lost an entry (code " + std::to_string(err) + ")");
         op.balanced = (int64_t)done + empty;  // empty slabs are trivially conflict-free
     }
-    const int eb = vdt == XCT_F32 ? 6 : 4;
+    const int64_t eb = (int64_t)entry_bytes(vdt);
     op.bytes = op.padded * eb + (int64_t)sizeof(int64_t) * (nlen + 1) + (int64_t)sizeof(int32_t) * op.n_list +
                (int64_t)sizeof(int32_t) * 2 * (nb + 1);
     return XCT_OK;
@@ -1090,13 +1122,15 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     xct_build_opts o = {};
     if (opts) o = *opts;
     const int W = o.tile_waves ? o.tile_waves : 16;
-    const int F = o.fuse ? o.fuse : 16;
+    const int F = o.fuse ? o.fuse : (value_dtype == XCT_F64 ? 8 : 16);
     int lds = o.lds_bytes;
     if (W < 1 || (W > 16 && W != 32)) return fail(XCT_ERR_INVALID, "tile_waves must be in [1, 16] or 32");
     if (F != 1 && F != 2 && F != 4 && F != 8 && F != 16 && F != 32)
         return fail(XCT_ERR_INVALID, "fuse must be 1, 2, 4, 8, 16 or 32");
-    if (F == 32 && (value_dtype == XCT_F32 || W > 16))
+    if (F == 32 && (value_dtype == XCT_F32 || value_dtype == XCT_F64 || W > 16))
         return fail(XCT_ERR_UNSUPPORTED, "32 fused slices need a 16-bit matrix and at most 16 row tiles per workgroup");
+    if (F == 16 && value_dtype == XCT_F64)
+        return fail(XCT_ERR_UNSUPPORTED, "FP64 matrices fuse at most 8 slices (64-byte staged rows)");
     const int per_tile = kTileSlots * F * elem_bytes(value_dtype);
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
@@ -1254,6 +1288,7 @@ static int matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t 
     std::vector<int64_t> slab;
     std::vector<uint16_t> slot;
     std::vector<float> val;
+    std::vector<double> val64;
     std::vector<uint32_t> packed;
     int rc = download(blk_stage, op.blk_stage, op.n_blocks + 1);
     if (!rc) rc = download(blk_tile, op.blk_tile, op.n_blocks + 1);
@@ -1264,6 +1299,9 @@ static int matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t 
     if (!rc && m->vdt == XCT_F32) {
         rc = download(slot, op.slot, op.padded * 3);  // the whole buffer, 6 B per entry
         if (!rc) val.assign((float *)slot.data(), (float *)slot.data() + op.padded * 3 / 2);
+    } else if (!rc && m->vdt == XCT_F64) {
+        rc = download(slot, op.slot, op.padded * 5);  // the whole buffer, 10 B per entry
+        if (!rc) val64.assign((double *)slot.data(), (double *)slot.data() + op.padded * 5 / 4);
     } else if (!rc) {
         rc = download(packed, op.packed, op.padded);
     }
@@ -1290,6 +1328,10 @@ static int matrix_to_coo(const xct_matrix *m, int which, int32_t *rows, int32_t 
                                 const int64_t li = (int64_t)lane * kGroup + q;
                                 sidx = slot[g * 768 + li];
                                 v = val[g * 384 + 128 + li];
+                            } else if (m->vdt == XCT_F64) {
+                                const int64_t li = (int64_t)lane * kGroup + q;
+                                sidx = slot[g * 1280 + li];
+                                v = (float)val64[g * 320 + 64 + li];  // decoded lengths are FP32
                             } else {
                                 sidx = packed[idx] >> 16;
                                 const uint16_t bits = (uint16_t)(packed[idx] & 0xffff);

@@ -63,7 +63,7 @@ static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base,
     c.s = (float *)take(sizeof(float) * c.nv * c.n_mb);
     c.r = (float *)take(sizeof(float) * c.ns * c.n_mb);
     c.q = (float *)take(sizeof(float) * c.ns * c.n_mb);
-    if (m->vdt != XCT_F32) c.op16 = take(2 * (size_t)std::max(c.nv, c.ns));
+    if (m->vdt == XCT_F16 || m->vdt == XCT_BF16) c.op16 = take(2 * (size_t)std::max(c.nv, c.ns));
     c.dotp = (double *)take(sizeof(double) * (size_t)c.n_mb * kVecBlocks * c.F);
     c.sqp = (double *)take(sizeof(double) * (size_t)c.n_mb * c.sq_stride * c.F);
     c.gamma = (double *)take(sizeof(double) * c.Bp);
@@ -331,6 +331,7 @@ extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, f
     if (!m || !y || !x || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
     if (batch < 1 || iters < 0) return fail(XCT_ERR_INVALID, "batch must be >= 1 and iters >= 0");
     if (!valid_dtype(y_dtype)) return fail(XCT_ERR_INVALID, "bad y dtype");
+    if (m->vdt == XCT_F64) return fail(XCT_ERR_UNSUPPORTED, "CGLS runs on FP32, FP16 and BF16 matrices");
     if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
     Cgls c;
     c.m = m;

@@ -59,12 +59,16 @@ struct OpPlan {
     //  F32 format: a group is 1536 bytes, 64 lanes x 4 u16 slots (512 B) then
     //    64 lanes x 4 f32 lengths (1 KB); slot of (g, lane, q) is
     //    slot[g*768 + lane*4 + q], its length val[g*384 + 128 + lane*4 + q];
+    //  F64 format: a group is 2560 bytes, 64 lanes x 4 u16 slots (512 B) then
+    //    64 lanes x 4 f64 lengths (2 KB); slot of (g, lane, q) is
+    //    slot[g*1280 + lane*4 + q], its length val64[g*320 + 64 + lane*4 + q];
     //  F16/BF16 format: a group is 1024 bytes, packed[(g*64 + lane)*4 + q] =
     //    slot << 16 | value bits.
-    // slot, val and packed are views of ent.
+    // slot, val, val64 and packed are views of ent.
     void *ent = nullptr;
     uint16_t *slot = nullptr;
     float *val = nullptr;
+    double *val64 = nullptr;
     uint32_t *packed = nullptr;
     int64_t nnz = 0, padded = 0, staged_slots = 0, bytes = 0;
     int64_t n_slabs = 0, balanced = 0;  // (stage, wavefront) slabs; those reordered against bank conflicts
@@ -120,8 +124,11 @@ void dev_free(void *p);
                                std::string(#expr) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
-inline int elem_bytes(xct_dtype d) { return d == XCT_F32 ? 4 : 2; }
-inline bool valid_dtype(int d) { return d == XCT_F32 || d == XCT_F16 || d == XCT_BF16; }
+inline int elem_bytes(xct_dtype d) { return d == XCT_F64 ? 8 : d == XCT_F32 ? 4 : 2; }
+inline bool valid_dtype(int d) { return d == XCT_F32 || d == XCT_F16 || d == XCT_BF16 || d == XCT_F64; }
+// Stored bytes per matrix entry: a 16-bit stage-local slot plus the value
+// (FP32, FP64), or slot and 16-bit value packed in one word.
+inline size_t entry_bytes(xct_dtype d) { return d == XCT_F64 ? 10 : d == XCT_F32 ? 6 : 4; }
 
 // Fused slice count used for a batch: the smallest supported F >= min(batch, fuse).
 inline int run_fuse(int batch, int fuse) {
@@ -135,7 +142,7 @@ inline int run_fuse(int batch, int fuse) {
 struct SpmmLaunch {
     const OpPlan *op;
     const void *xin;      // internal layout [in tiles][64][F], storage dtype
-    float *yout;          // internal layout [row tiles][64][F], FP32
+    void *yout;           // internal layout [row tiles][64][F], FP32 (FP64 for FP64 matrices)
     const float *scale;   // [F] per-slice output scale or nullptr
     double *sq_partial;   // [n_blocks][F] per-block sums of squared outputs or nullptr
     int F;

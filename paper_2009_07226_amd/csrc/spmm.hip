@@ -37,6 +37,7 @@ namespace xct {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float h16_to_f32(uint32_t bits) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
@@ -48,6 +49,14 @@ template <int FMT> struct Stor;
 template <> struct Stor<XCT_F32> { typedef float T; };
 template <> struct Stor<XCT_F16> { typedef uint16_t T; };
 template <> struct Stor<XCT_BF16> { typedef uint16_t T; };
+template <> struct Stor<XCT_F64> { typedef double T; };
+
+// Accumulator (and output) type: FP64 for FP64 matrices, else FP32.
+template <int FMT> struct Acc { typedef float T; };
+template <> struct Acc<XCT_F64> { typedef double T; };
+
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return fma(a, b, c); }
 
 // Shape of one staged row (the F operands of one slot).
 template <int FMT, int F>
@@ -58,10 +67,16 @@ struct RowShape {
     static constexpr int SPC = F / CH;                // slices per chunk
 };
 
-// Expand one 16-byte chunk (or a sub-16-byte row) into SPC FP32 values.
+// Expand one 16-byte chunk (or a sub-16-byte row) into SPC values of the
+// accumulator type.
 template <int FMT, int SPC>
-__device__ __forceinline__ void expand(const u32x4 w, float (&x)[SPC]) {
-    if constexpr (FMT == XCT_F32) {
+__device__ __forceinline__ void expand(const u32x4 w, typename Acc<FMT>::T (&x)[SPC]) {
+    if constexpr (FMT == XCT_F64) {
+        const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int t = 0; t < SPC; ++t)
+            x[t] = __builtin_bit_cast(double, (uint64_t)u[2 * t] | ((uint64_t)u[2 * t + 1] << 32));
+    } else if constexpr (FMT == XCT_F32) {
         const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
         for (int t = 0; t < SPC; ++t) x[t] = __builtin_bit_cast(float, u[t]);
@@ -121,7 +136,7 @@ struct SpmmArgs {
     const float *val;
     const uint32_t *packed;
     const void *xin;
-    float *yout;
+    void *yout;  // FP32 sums, FP64 for FP64 matrices
     const float *scale;
     double *sq_partial;
     int64_t n_row_tiles;
@@ -134,10 +149,12 @@ template <int FMT> struct Group;
 template <> struct Group<XCT_F32> { u32x2 s; f32x4 v; };
 template <> struct Group<XCT_F16> { u32x4 p; };
 template <> struct Group<XCT_BF16> { u32x4 p; };
+template <> struct Group<XCT_F64> { u32x2 s; u32x4 v01, v23; };
 
 // Bytes of one group (64 lanes x kGroup entries; layout: see OpPlan).
 template <int FMT> struct GroupBytes { static constexpr int value = 1024; };
 template <> struct GroupBytes<XCT_F32> { static constexpr int value = 1536; };
+template <> struct GroupBytes<XCT_F64> { static constexpr int value = 2560; };
 
 // Lane `lane`'s part of group g of a wavefront's entry stream, read through
 // a buffer descriptor of the stream: the group offset is a scalar operand, so
@@ -152,6 +169,11 @@ __device__ __forceinline__ Group<FMT> load_group(__amdgpu_buffer_rsrc_t rs, int 
     if constexpr (FMT == XCT_F32) {
         r.s = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, so, kNonTemporal));
         r.v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 512 + lane * 16, so, kNonTemporal));
+    } else if constexpr (FMT == XCT_F64) {
+        r.s = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, so, kNonTemporal));
+        r.v01 = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 512 + lane * 32, so, kNonTemporal));
+        r.v23 =
+            __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 528 + lane * 32, so, kNonTemporal));
     } else {
         r.p = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, so, kNonTemporal));
     }
@@ -160,12 +182,20 @@ __device__ __forceinline__ Group<FMT> load_group(__amdgpu_buffer_rsrc_t rs, int 
 
 template <int FMT, int F, int KB>
 __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&cb)[RowShape<FMT, F>::CH],
-                                          float (&acc)[F]) {
+                                          typename Acc<FMT>::T (&acc)[F]) {
     typedef RowShape<FMT, F> R;
+    typedef typename Acc<FMT>::T AT;
     // the word holding step q's slot, and whether it is the high half
     uint32_t sw[kGroup];
-    float v[kGroup];
-    if constexpr (FMT == XCT_F32) {
+    AT v[kGroup];
+    if constexpr (FMT == XCT_F64) {
+        sw[0] = sw[1] = g.s.x;
+        sw[2] = sw[3] = g.s.y;
+        v[0] = __builtin_bit_cast(double, (uint64_t)g.v01.x | ((uint64_t)g.v01.y << 32));
+        v[1] = __builtin_bit_cast(double, (uint64_t)g.v01.z | ((uint64_t)g.v01.w << 32));
+        v[2] = __builtin_bit_cast(double, (uint64_t)g.v23.x | ((uint64_t)g.v23.y << 32));
+        v[3] = __builtin_bit_cast(double, (uint64_t)g.v23.z | ((uint64_t)g.v23.w << 32));
+    } else if constexpr (FMT == XCT_F32) {
         sw[0] = sw[1] = g.s.x;
         sw[2] = sw[3] = g.s.y;
         v[0] = g.v.x;
@@ -189,7 +219,7 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             const int q = q0 + k;
-            constexpr bool kHiAlways = FMT != XCT_F32;  // 16-bit entries: slot << 16 | value
+            constexpr bool kHiAlways = FMT == XCT_F16 || FMT == XCT_BF16;  // 16-bit entries: slot << 16 | value
 #pragma unroll
             for (int j = 0; j < R::CH; ++j) {
                 const uint32_t ad = (kHiAlways || (q & 1)) ? row_addr<R::RB, true>(sw[q], cb[j])
@@ -205,11 +235,11 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&
         for (int k = 0; k < KB; ++k) {
 #pragma unroll
             for (int j = 0; j < R::CH; ++j) {
-                float x[R::SPC];
+                AT x[R::SPC];
                 expand<FMT, R::SPC>(w[k][j], x);
 #pragma unroll
                 for (int t = 0; t < R::SPC; ++t)
-                    acc[j * R::SPC + t] = fmaf(v[q0 + k], x[t], acc[j * R::SPC + t]);
+                    acc[j * R::SPC + t] = fma_acc(v[q0 + k], x[t], acc[j * R::SPC + t]);
             }
         }
     }
@@ -295,12 +325,15 @@ __device__ __forceinline__ void prio_for_remaining(int rem) {
 // slot only once consumed: D = 4 measured best there (2: +2%, 3: +0.3%).
 template <int FMT> struct RingDepth { static constexpr int value = 4; };
 template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
+template <> struct RingDepth<XCT_F64> { static constexpr int value = 3; };  // 10 registers a group
 
 // LDS reads issued together: the whole group, or half of it when a
 // wavefront holds two FP32 accumulator sets of 16 slices (register budget).
 template <int FMT, int F, int RT> struct ReadBatch { static constexpr int value = 4; };
 template <> struct ReadBatch<XCT_F32, 16, 2> { static constexpr int value = 2; };
 template <> struct ReadBatch<XCT_F16, 32, 1> { static constexpr int value = 2; };
+template <int F> struct ReadBatch<XCT_F64, F, 1> { static constexpr int value = 2; };
+template <int F> struct ReadBatch<XCT_F64, F, 2> { static constexpr int value = 1; };
 template <> struct ReadBatch<XCT_BF16, 32, 1> { static constexpr int value = 2; };
 
 // RT: row tiles per wavefront (a.W / RT wavefronts per block); H16: FP16
@@ -332,12 +365,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         cb[j] = lds_addr(smem) + coff[j];
     }
     static_assert(!H16 || (FMT == XCT_F16 && F >= 2), "FP16 arithmetic needs an FP16 matrix and F >= 2");
-    float acc[RT][H16 ? 1 : F];
+    typedef typename Acc<FMT>::T AT;
+    AT acc[RT][H16 ? 1 : F];
     h2 acc2[RT][H16 ? F / 2 : 1];
 #pragma unroll
     for (int h = 0; h < RT; ++h) {
 #pragma unroll
-        for (int f = 0; f < (H16 ? 1 : F); ++f) acc[h][f] = 0.f;
+        for (int f = 0; f < (H16 ? 1 : F); ++f) acc[h][f] = (AT)0;
 #pragma unroll
         for (int f = 0; f < (H16 ? F / 2 : 1); ++f) acc2[h][f] = h2{(_Float16)0, (_Float16)0};
     }
@@ -362,7 +396,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     const int ne = (int)(ge - gw);
     const int64_t gfirst = ne > 0 ? gw : (gw > 0 ? gw - 1 : 0);
     const char *ent_w =
-        (const char *)(FMT == XCT_F32 ? (const void *)a.slot : (const void *)a.packed) + gfirst * GB;
+        (const char *)(FMT == XCT_F32 || FMT == XCT_F64 ? (const void *)a.slot : (const void *)a.packed) + gfirst * GB;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)ent_w, (short)0, (ne > 0 ? ne : 1) * GB, kRsrcWord3);
     const int rlast = ne > 0 ? ne - 1 : 0;
@@ -378,7 +412,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         ++lg;
         return g;
     };
-    constexpr bool kFlat = FMT == XCT_F32;
+    constexpr bool kFlat = FMT == XCT_F32 || FMT == XCT_F64;
     Group<FMT> e[D];
     int sg[D];
 #pragma unroll
@@ -585,7 +619,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     for (int f = 0; f < F; ++f) sq[f] = 0.0;
 #pragma unroll
     for (int h = 0; h < RT; ++h) {
-        float af[F];  // the row's sums in accumulator order, FP32
+        AT af[F];  // the row's sums in accumulator order
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if constexpr (H16)
@@ -593,12 +627,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
             else
                 af[f] = acc[h][f];
         }
-        float y[F];
+        AT y[F];
 #pragma unroll
         for (int c = 0; c < R::CH; ++c) {
 #pragma unroll
             for (int t = 0; t < R::SPC; ++t) {
-                float v = af[t];
+                AT v = af[t];
 #pragma unroll
                 for (int j = 1; j < R::CH; ++j) v = (coff[j] == c * 16) ? af[j * R::SPC + t] : v;
                 y[c * R::SPC + t] = v;
@@ -610,8 +644,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
         }
         const int64_t rt = (int64_t)b * W + h * P + wave;
         if (rt < a.n_row_tiles) {
-            float *out = a.yout + (rt * kTileSlots + lane_slot(lane, a.lanes)) * F;
-            if constexpr (F >= 4) {
+            AT *out = (AT *)a.yout + (rt * kTileSlots + lane_slot(lane, a.lanes)) * F;
+            if constexpr (FMT == XCT_F64 && F >= 2) {
+#pragma unroll
+                for (int q = 0; q < F / 2; ++q) ((f64x2 *)out)[q] = f64x2{y[2 * q], y[2 * q + 1]};
+            } else if constexpr (FMT != XCT_F64 && F >= 4) {
 #pragma unroll
                 for (int q = 0; q < F / 4; ++q)
                     ((f32x4 *)out)[q] = f32x4{y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
@@ -715,11 +752,14 @@ static int launch_rt(const SpmmLaunch &L, hipStream_t st) {
         case 2: return launch_arith<FMT, 2, RT>(L, st);
         case 4: return launch_arith<FMT, 4, RT>(L, st);
         case 8: return launch_arith<FMT, 8, RT>(L, st);
-        case 16: return launch_arith<FMT, 16, RT>(L, st);
+        case 16:
+            // FP64 rows of 16 slices would be 128 bytes: FP64 fuses at most 8
+            if constexpr (FMT != XCT_F64) return launch_arith<FMT, 16, RT>(L, st);
+            return fail(XCT_ERR_UNSUPPORTED, "FP64 matrices fuse at most 8 slices");
         case 32:
             // 32 fused slices: 16-bit operands only (64-byte staged rows, as
             // FP32 at 16) and one row tile per wavefront (32 accumulators)
-            if constexpr (FMT != XCT_F32 && RT == 1) return launch_arith<FMT, 32, RT>(L, st);
+            if constexpr ((FMT == XCT_F16 || FMT == XCT_BF16) && RT == 1) return launch_arith<FMT, 32, RT>(L, st);
             return fail(XCT_ERR_UNSUPPORTED, "32 fused slices need a 16-bit matrix and one row tile per wavefront");
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
@@ -739,6 +779,7 @@ int launch_spmm(const SpmmLaunch &L, hipStream_t st) {
         case XCT_F32: return launch_fmt<XCT_F32>(L, st);
         case XCT_F16: return launch_fmt<XCT_F16>(L, st);
         case XCT_BF16: return launch_fmt<XCT_BF16>(L, st);
+        case XCT_F64: return launch_fmt<XCT_F64>(L, st);
         default: return fail(XCT_ERR_INVALID, "bad value dtype");
     }
 }
@@ -747,6 +788,7 @@ int launch_spmm(const SpmmLaunch &L, hipStream_t st) {
 
 __device__ __forceinline__ float load_io(const void *p, int64_t i, int io) {
     if (io == XCT_F32) return ((const float *)p)[i];
+    if (io == XCT_F64) return (float)((const double *)p)[i];
     const uint16_t b = ((const uint16_t *)p)[i];
     return io == XCT_F16 ? h16_to_f32(b) : bf16_to_f32(b);
 }
@@ -764,6 +806,8 @@ __device__ __forceinline__ uint32_t f32_to_bf16(float v) {
 __device__ __forceinline__ void store_io(void *p, int64_t i, float v, int io) {
     if (io == XCT_F32)
         ((float *)p)[i] = v;
+    else if (io == XCT_F64)
+        ((double *)p)[i] = (double)v;
     else
         ((uint16_t *)p)[i] = (uint16_t)(io == XCT_F16 ? f32_to_h16(v) : f32_to_bf16(v));
 }
@@ -829,6 +873,76 @@ __global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const
 #pragma unroll
             for (int f = 0; f < F; ++f) dst[f] = h[f];
         }
+    }
+}
+
+// FP64 matrices: the same conversions with FP64 rows (any io dtype; FP64 io
+// keeps every bit, narrower io is rounded once, nearest-even).
+__device__ __forceinline__ double load_io64(const void *p, int64_t i, int io) {
+    if (io == XCT_F64) return ((const double *)p)[i];
+    return (double)load_io(p, i, io);
+}
+
+__device__ __forceinline__ void store_io64(void *p, int64_t i, double v, int io) {
+    if (io == XCT_F64)
+        ((double *)p)[i] = v;
+    else
+        store_io(p, i, (float)v, io);
+}
+
+template <int F>
+__global__ void k_to_internal64(ConvArgs c, const void *nat, double *internal) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= c.n_tiles * kTileSlots) return;
+    const int64_t rank = t >> 6;
+    const int o = (int)(t & 63);
+    const int coord = c.coord_of[rank];
+    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    const bool in = row < c.H && col < c.Wd;
+    const int64_t plane = (int64_t)c.H * c.Wd;
+    const int64_t pix = (int64_t)row * c.Wd + col;
+    double v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int s = c.s0 + f;
+        v[f] = (in && s < c.batch) ? load_io64(nat, (int64_t)s * plane + pix, c.io) : 0.0;
+    }
+    double *dst = internal + t * F;
+    if constexpr (F >= 2) {
+#pragma unroll
+        for (int q = 0; q < F / 2; ++q) ((f64x2 *)dst)[q] = f64x2{v[2 * q], v[2 * q + 1]};
+    } else {
+        dst[0] = v[0];
+    }
+}
+
+template <int F>
+__global__ void k_from_internal64(ConvArgs c, const double *internal, void *nat) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= c.n_tiles * kTileSlots) return;
+    const int64_t rank = t >> 6;
+    const int o = (int)(t & 63);
+    const int coord = c.coord_of[rank];
+    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    if (row >= c.H || col >= c.Wd) return;
+    const int64_t plane = (int64_t)c.H * c.Wd;
+    const int64_t pix = (int64_t)row * c.Wd + col;
+    double v[F];
+    const double *src = internal + t * F;
+    if constexpr (F >= 2) {
+#pragma unroll
+        for (int q = 0; q < F / 2; ++q) {
+            const f64x2 w = ((const f64x2 *)src)[q];
+            v[2 * q] = w.x;
+            v[2 * q + 1] = w.y;
+        }
+    } else {
+        v[0] = src[0];
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const int s = c.s0 + f;
+        if (s < c.batch) store_io64(nat, (int64_t)s * plane + pix, v[f], c.io);
     }
 }
 
@@ -926,6 +1040,18 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
     const ConvArgs c = conv_args(g, batch, s0, F, io, storage);
     const int64_t n = g.n_tiles * kTileSlots;
     const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    if (storage == XCT_F64) {
+        double *d = (double *)internal;
+        switch (F) {
+            case 1: hipLaunchKernelGGL(k_to_internal64<1>, grid, blk, 0, st, c, nat, d); break;
+            case 2: hipLaunchKernelGGL(k_to_internal64<2>, grid, blk, 0, st, c, nat, d); break;
+            case 4: hipLaunchKernelGGL(k_to_internal64<4>, grid, blk, 0, st, c, nat, d); break;
+            case 8: hipLaunchKernelGGL(k_to_internal64<8>, grid, blk, 0, st, c, nat, d); break;
+            default: return fail(XCT_ERR_INVALID, "unsupported fused slice count for FP64");
+        }
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
     switch (F) {
         case 1: hipLaunchKernelGGL(k_to_internal<1>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         case 2: hipLaunchKernelGGL(k_to_internal<2>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
@@ -934,6 +1060,23 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
         case 16: hipLaunchKernelGGL(k_to_internal<16>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         case 32: hipLaunchKernelGGL(k_to_internal<32>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
+    }
+    XCT_HIP_TRY(hipGetLastError());
+    return XCT_OK;
+}
+
+// FP64 sums (FP64 matrices) to the natural layout
+static int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat,
+                                  xct_dtype io, hipStream_t st) {
+    const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F64);
+    const int64_t n = g.n_tiles * kTileSlots;
+    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    switch (F) {
+        case 1: hipLaunchKernelGGL(k_from_internal64<1>, grid, blk, 0, st, c, internal, nat); break;
+        case 2: hipLaunchKernelGGL(k_from_internal64<2>, grid, blk, 0, st, c, internal, nat); break;
+        case 4: hipLaunchKernelGGL(k_from_internal64<4>, grid, blk, 0, st, c, internal, nat); break;
+        case 8: hipLaunchKernelGGL(k_from_internal64<8>, grid, blk, 0, st, c, internal, nat); break;
+        default: return fail(XCT_ERR_INVALID, "unsupported fused slice count for FP64");
     }
     XCT_HIP_TRY(hipGetLastError());
     return XCT_OK;
@@ -979,7 +1122,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct SpmmWs {
     void *in;
-    float *out;
+    void *out;  // FP32 sums, FP64 for FP64 matrices
     uint32_t *amax;
     float *scale, *inv;
 };
@@ -989,11 +1132,11 @@ struct SpmmWs {
 static size_t spmm_ws_layout_f(const xct_matrix *m, int F, char *base, SpmmWs *w) {
     const int64_t tiles = std::max(m->vol.n_tiles, m->sino.n_tiles);
     const size_t in_b = align256((size_t)tiles * kTileSlots * F * elem_bytes(m->vdt));
-    const size_t out_b = align256((size_t)tiles * kTileSlots * F * sizeof(float));
+    const size_t out_b = align256((size_t)tiles * kTileSlots * F * (m->vdt == XCT_F64 ? sizeof(double) : sizeof(float)));
     const size_t small = align256(sizeof(uint32_t) * kMaxFuse) * 3;
     if (w) {
         w->in = base;
-        w->out = (float *)(base + in_b);
+        w->out = base + in_b;
         char *p = base + in_b + out_b;
         w->amax = (uint32_t *)p;
         w->scale = (float *)(p + align256(sizeof(uint32_t) * kMaxFuse));
@@ -1016,7 +1159,7 @@ static int spmm_call_f(const xct_matrix *m, int dir, const void *src, void *dst,
     const Grid &gout = dir ? m->vol : m->sino;
     SpmmWs w;
     spmm_ws_layout_f(m, F, (char *)workspace, &w);
-    const bool norm = m->vdt != XCT_F32;
+    const bool norm = m->vdt == XCT_F16 || m->vdt == XCT_BF16;
     if (norm) {
         hipLaunchKernelGGL(k_clear_amax, dim3(1), dim3(64), 0, st, w.amax, kMaxFuse);
         XCT_HIP_TRY(hipGetLastError());
@@ -1032,7 +1175,8 @@ static int spmm_call_f(const xct_matrix *m, int dir, const void *src, void *dst,
         SpmmLaunch L{&op, w.in, w.out, norm ? w.scale : nullptr, nullptr, F, m->vdt, m->remap};
         rc = launch_spmm(L, st);
         if (rc) return rc;
-        rc = launch_from_internal(gout, w.out, batch, s0, F, dst, io, st);
+        rc = m->vdt == XCT_F64 ? launch_from_internal64(gout, (const double *)w.out, batch, s0, F, dst, io, st)
+                               : launch_from_internal(gout, (const float *)w.out, batch, s0, F, dst, io, st);
         if (rc) return rc;
     }
     return XCT_OK;

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n) {
 }
 
 // Number of elements of v that are NaN or infinite (dt: 0 FP32, 1 FP16,
-// 2 BF16), added into *count (cleared by k_zero_count first).
+// 2 BF16, 3 FP64), added into *count (cleared by k_zero_count first).
 __global__ void k_zero_count(unsigned long long *count) { *count = 0ull; }
 
 __global__ void __launch_bounds__(256) k_count_nonfinite(const void *v, int64_t n, int dt,
@@ -36,6 +36,8 @@ __global__ void __launch_bounds__(256) k_count_nonfinite(const void *v, int64_t 
         bool bad;
         if (dt == XCT_F32) {
             bad = (__float_as_uint(((const float *)v)[i]) & 0x7f800000u) == 0x7f800000u;
+        } else if (dt == XCT_F64) {
+            bad = (((const uint64_t *)v)[i] & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
         } else {
             const uint16_t h = ((const uint16_t *)v)[i];
             bad = dt == XCT_F16 ? (h & 0x7c00u) == 0x7c00u : (h & 0x7f80u) == 0x7f80u;

@@ -17,9 +17,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxct.so")
 
-F32, F16, BF16 = 0, 1, 2
-_TORCH_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
-_NAME_DT = {"f32": F32, "float32": F32, "f16": F16, "float16": F16, "bf16": BF16, "bfloat16": BF16}
+F32, F16, BF16, F64 = 0, 1, 2, 3
+_TORCH_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16, torch.float64: F64}
+_NAME_DT = {"f32": F32, "float32": F32, "f16": F16, "float16": F16, "bf16": BF16, "bfloat16": BF16,
+            "f64": F64, "float64": F64}
 
 EXPORTS = ("xct_build_matrix", "xct_free_matrix", "xct_matrix_info", "xct_spmm_workspace_bytes",
            "xct_project", "xct_backproject", "xct_cgls_workspace_bytes", "xct_cgls",

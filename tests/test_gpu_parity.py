@@ -508,3 +508,62 @@ def test_fp16_arithmetic_options():
     A16h = gpu_matrix(37, 23, 41, "f16", arith=1)
     x = phantoms.ellipse_batch(37, 1, 4, seed=5).float().cuda()
     assert torch.equal(xct.project(A16, x), xct.project(A16h, x))
+
+
+# ---- FP64 matrices (the double-precision variant) -------------------------------
+
+@pytest.mark.parametrize("N,M,C", GEOMS)
+def test_fp64_products_match_oracle(N, M, C):
+    # FP64 lengths, operands and sums: within 1e-12 of the oracle per slice,
+    # ragged batches around the 8-slice pass
+    A = gpu_matrix(N, M, C, "f64")
+    info = A.info()
+    assert info["fuse"] == 8 and info["A"]["nnz"] == oracle_mats(N, M, C)[0].nnz
+    Ao, ATo = oracle_mats(N, M, C)
+    for B in (1, 8, 9):
+        x = phantoms.ellipse_batch(N, B, 6, seed=500 + B).double()
+        y = xct.project(A, x.cuda())
+        assert y.dtype == torch.float64
+        e = rel_err(y.cpu().numpy(), oracle.project(Ao, x.numpy().reshape(B, -1)))
+        yin = torch.from_numpy(oracle.project(Ao, x.numpy().reshape(B, -1))).reshape(B, M, C)
+        yin = yin + 0.1 * torch.randn(B, M, C, generator=torch.Generator().manual_seed(B), dtype=torch.float64)
+        xb = xct.backproject(A, yin.cuda())
+        eb = rel_err(xb.cpu().numpy(), oracle.backproject(ATo, yin.numpy()))
+        banner(f"f64 N={N} M={M} C={C} B={B}: projection {e.max():.2e} backprojection {eb.max():.2e}")
+        assert e.max() <= 1e-12 and eb.max() <= 1e-12
+
+
+def test_fp64_entries_and_io():
+    N, M, C = 37, 23, 41
+    A = gpu_matrix(N, M, C, "f64")
+    Ao, ATo = oracle_mats(N, M, C)
+    for which, ref in ((0, Ao.tocoo()), (1, ATo.tocoo())):
+        r, c, v = A.to_coo(which)  # lengths decoded as FP32
+        gk = r.astype(np.int64) * ref.shape[1] + c
+        rk = ref.row.astype(np.int64) * ref.shape[1] + ref.col
+        og, oo = np.argsort(gk), np.argsort(rk)
+        np.testing.assert_array_equal(gk[og], rk[oo])
+        ov = ref.data[oo].astype(np.float32)
+        assert np.all(np.abs(v[og] - ov) <= np.spacing(ov))
+    # FP32 io on an FP64 matrix: the operand rounded once, sums in FP64
+    x = phantoms.ellipse_batch(N, 3, 5, seed=41).float()
+    y = xct.project(A, x.cuda())
+    assert y.dtype == torch.float32
+    assert rel_err(y.cpu().numpy(), oracle.project(Ao, x.double().numpy().reshape(3, -1))).max() <= 1e-6
+    # adjoint identity in FP64
+    g = torch.Generator(device="cuda").manual_seed(5)
+    xr = torch.randn(2, N, N, device="cuda", dtype=torch.float64, generator=g)
+    yr = torch.randn(2, M, C, device="cuda", dtype=torch.float64, generator=g)
+    lhs = (xct.project(A, xr) * yr).sum(dim=(1, 2))
+    rhs = (xr * xct.backproject(A, yr)).sum(dim=(1, 2))
+    assert float(((lhs - rhs).abs() / lhs.abs().clamp_min(1e-300)).max()) <= 1e-12
+
+
+def test_fp64_limits():
+    with pytest.raises(xct.XctError) as e:
+        xct.Matrix(16, 12, 16, "f64", fuse=16)
+    assert e.value.code == -4
+    A = gpu_matrix(16, 12, 16, "f64")
+    with pytest.raises(xct.XctError) as e:
+        xct.cgls(A, torch.rand(1, 12, 16, device="cuda"), 2)
+    assert e.value.code == -4
