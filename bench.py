@@ -537,7 +537,24 @@ def main():
         out["projected_gradient"] = {"iters": pg_it, "lam": lam, "eps": eps, "fp16_s_per_iter": round(tpg, 6),
                                      "vs_spmm_pair": round(tpg / (s16["ms_per_step"] * 1e-3), 3)}
         A16.free()
-        del A16, yc
+        del A16
+        # the paper's precision comparison (Sec. IV, CG time and convergence by
+        # precision): CGLS with an FP64 matrix (FP64 vectors and sums) and with
+        # FP16 arithmetic (FP16 matrix, packed FP16 sums), beside FP32 and mixed
+        prec = {}
+        for name, vdt, bopts in (("fp64", "f64", opts), ("half", "f16", dict(opts, arith=1))):
+            log(f"CGLS {name}")
+            Ap = xct.Matrix(N, M, C, vdt, **bopts)
+            tp = cgls_s_per_iter(xct, torch, Ap, yc, it)
+            _, resp = cgls_history(Ap)
+            prec[name] = {"s_per_iter": round(tp, 6),
+                          "residual_median": [float(np.median(resp[k])) for k in checkpoints]}
+            Ap.free()
+            del Ap
+        out["cgls"]["precision"] = dict(prec, k=checkpoints,
+                                        note="mixed = FP16 storage with FP32 sums (fp16 above); half = packed "
+                                             "FP16 sums; fp64 = FP64 matrix, vectors and sums")
+        del yc
     else:
         A.free()
         del A

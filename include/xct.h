@@ -77,8 +77,10 @@ typedef struct {
     int lds_bytes;  /* LDS bytes per workgroup at F = fuse: one stage of staged input
                        (T = lds_bytes / (64 * F * element size) input tiles, at most 1024);
                        default: all of the device's LDS per workgroup (160 KiB on gfx950) */
-    int xcd_remap;  /* 1 (default): consecutive workgroups of the Hilbert order run on the
-                       same XCD; -1: plain order */
+    int xcd_remap;  /* how workgroups map to the 8 XCDs (each with its own L2): runs of n
+                       consecutive workgroups of the Hilbert order dealt to the XCDs in turn,
+                       n >= 2 as given, 4 for 0 (default); 1 one contiguous run per XCD;
+                       -1 plain order */
     int stage_order; /* order in which a workgroup stages its input tiles:
                         0 (default) sweep: for A, by distance along the workgroup's mean ray
                           direction; for A^T, angle-major;
@@ -132,7 +134,7 @@ typedef struct {
  *               4 B, Sec. III-C "data packing"), or XCT_F64 (index + FP64
  *               value, 10 B per entry, FP64 operand and sums: the
  *               double-precision variant of Sec. IV; at most 8 fused
- *               slices, and not for xct_cgls); lengths are computed in
+ *               slices); lengths are computed in
  *               FP64 and rounded to nearest-even once.
  *   opts        nullable; see xct_build_opts
  *   stream      stream for the build kernels; the call returns after they finish
@@ -260,7 +262,9 @@ size_t xct_cgls_workspace_bytes(const xct_matrix *A, int batch, int iters);
  *              else 0
  * Solver vectors are FP32 and the per-slice scalars FP64.  With an F16/BF16
  * matrix the operand of each product is max-norm scaled and rounded to
- * 16 bits (Sec. III-C).  When resid or status is given the call waits for
+ * 16 bits (Sec. III-C).  With an FP64 matrix the solver vectors and the
+ * products are FP64 (the double-precision variant of Sec. IV) and x is
+ * returned rounded to FP32.  When resid or status is given the call waits for
  * the stream before returning.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
  */
 int xct_cgls(const xct_matrix *A, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,

@@ -1144,6 +1144,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     int T = lds / per_tile;
     if (T > 1024) T = 1024;  // stage-local slots must fit 16 bits
     if (o.lane_order < 0 || o.lane_order > 1) return fail(XCT_ERR_INVALID, "lane_order must be 0 or 1");
+    if (o.xcd_remap < -1) return fail(XCT_ERR_INVALID, "xcd_remap must be -1, 0, 1 or a run length >= 2");
     if (o.slab_order < 0 || o.slab_order > 1) return fail(XCT_ERR_INVALID, "slab_order must be 0 or 1");
     if (o.arith < 0 || o.arith > 1) return fail(XCT_ERR_INVALID, "arith must be 0 or 1");
     if (o.arith == 1 && value_dtype != XCT_F16)
@@ -1163,7 +1164,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     m->C = n_channels;
     m->vdt = value_dtype;
     m->fuse = F;
-    m->remap = o.xcd_remap >= 0 ? 1 : 0;
+    m->remap = o.xcd_remap;  // resolved per launch (remap_chunk)
     hipStream_t st = (hipStream_t)stream;
     // host containers may throw; the C ABI returns a status instead
     int rc = XCT_OK;

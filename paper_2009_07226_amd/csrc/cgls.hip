@@ -29,10 +29,13 @@ constexpr int kVecBlocks = 1024;
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// T: the solver vectors' type, FP64 for FP64 matrices (the double-precision
+// variant), else FP32.
+template <class T>
 struct CglsWs {
     int F = 0, n_mb = 0, Bp = 0;
     int64_t nv = 0, ns = 0;  // elements of one group's volume / sinogram vector
-    float *x = nullptr, *p = nullptr, *s = nullptr, *r = nullptr, *q = nullptr;
+    T *x = nullptr, *p = nullptr, *s = nullptr, *r = nullptr, *q = nullptr;
     void *op16 = nullptr;    // one group's 16-bit operand (volume or sinogram sized)
     double *dotp = nullptr;  // [n_mb][kVecBlocks][F]
     double *sqp = nullptr;   // [n_mb][max blocks][F]
@@ -44,8 +47,9 @@ struct CglsWs {
     int64_t sq_stride = 0;    // max blocks
 };
 
-static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base, CglsWs *w) {
-    CglsWs c;
+template <class T>
+static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base, CglsWs<T> *w) {
+    CglsWs<T> c;
     c.F = run_fuse(batch, m->fuse);
     c.n_mb = (batch + c.F - 1) / c.F;
     c.Bp = c.n_mb * c.F;
@@ -58,11 +62,11 @@ static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base,
         off += al256(bytes);
         return base ? (void *)(base + o) : nullptr;
     };
-    c.x = (float *)take(sizeof(float) * c.nv * c.n_mb);
-    c.p = (float *)take(sizeof(float) * c.nv * c.n_mb);
-    c.s = (float *)take(sizeof(float) * c.nv * c.n_mb);
-    c.r = (float *)take(sizeof(float) * c.ns * c.n_mb);
-    c.q = (float *)take(sizeof(float) * c.ns * c.n_mb);
+    c.x = (T *)take(sizeof(T) * c.nv * c.n_mb);
+    c.p = (T *)take(sizeof(T) * c.nv * c.n_mb);
+    c.s = (T *)take(sizeof(T) * c.nv * c.n_mb);
+    c.r = (T *)take(sizeof(T) * c.ns * c.n_mb);
+    c.q = (T *)take(sizeof(T) * c.ns * c.n_mb);
     if (m->vdt == XCT_F16 || m->vdt == XCT_BF16) c.op16 = take(2 * (size_t)std::max(c.nv, c.ns));
     c.dotp = (double *)take(sizeof(double) * (size_t)c.n_mb * kVecBlocks * c.F);
     c.sqp = (double *)take(sizeof(double) * (size_t)c.n_mb * c.sq_stride * c.F);
@@ -96,7 +100,8 @@ __device__ __forceinline__ void block_partial(double acc, int F, double *part) {
     }
 }
 
-__global__ void k_sqnorm(const float *v, int64_t n, int F, double *part) {
+template <class T>
+__global__ void k_sqnorm(const T *v, int64_t n, int F, double *part) {
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double t = v[i];
@@ -120,16 +125,16 @@ __device__ __forceinline__ void block_max(float m, int F, uint32_t *amax) {
 
 // r -= alpha q, with block partials of |r|^2 (sinogram) and, when amax is
 // given, the per-slice max |r| (the next product's operand scale)
-__global__ void k_axpy_res(float *r, const float *q, int64_t n, int F, const double *alpha, double *part,
-                           uint32_t *amax) {
+template <class T>
+__global__ void k_axpy_res(T *r, const T *q, int64_t n, int F, const double *alpha, double *part, uint32_t *amax) {
     double acc = 0.0;
     float m = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float a = (float)alpha[i & (F - 1)];
-        const float t = fmaf(-a, q[i], r[i]);
+        const T a = (T)alpha[i & (F - 1)];
+        const T t = fma(-a, q[i], r[i]);
         r[i] = t;
         acc += (double)t * (double)t;
-        m = fmaxf(m, fabsf(t));
+        m = fmaxf(m, fabsf((float)t));
     }
     block_partial(acc, F, part);
     if (amax) block_max(m, F, amax);
@@ -138,16 +143,17 @@ __global__ void k_axpy_res(float *r, const float *q, int64_t n, int F, const dou
 // x += alpha p, then p = s + beta p, in one pass (the iterate's update is
 // deferred to here from the step where alpha is found: p is unchanged in
 // between); when amax is given, also the per-slice max |p| of the new p
-__global__ void k_update_xp(float *x, float *p, const float *s, int64_t n, int F, const double *alpha,
-                            const double *beta, uint32_t *amax) {
+template <class T>
+__global__ void k_update_xp(T *x, T *p, const T *s, int64_t n, int F, const double *alpha, const double *beta,
+                            uint32_t *amax) {
     float m = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float a = (float)alpha[i & (F - 1)], bt = (float)beta[i & (F - 1)];
-        const float pv = p[i];
-        if (a != 0.f) x[i] = fmaf(a, pv, x[i]);  // a stopped slice keeps its iterate, also if p is not finite
-        const float t = fmaf(bt, pv, s[i]);
+        const T a = (T)alpha[i & (F - 1)], bt = (T)beta[i & (F - 1)];
+        const T pv = p[i];
+        if (a != (T)0) x[i] = fma(a, pv, x[i]);  // a stopped slice keeps its iterate, also if p is not finite
+        const T t = fma(bt, pv, s[i]);
         p[i] = t;
-        m = fmaxf(m, fabsf(t));
+        m = fmaxf(m, fabsf((float)t));
     }
     if (amax) block_max(m, F, amax);
 }
@@ -252,9 +258,10 @@ __global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, do
 
 // ---- orchestration -----------------------------------------------------------
 
+template <class T>
 struct Cgls {
     const xct_matrix *m;
-    CglsWs w;
+    CglsWs<T> w;
     hipStream_t st;
     int grid_v, grid_s;
 
@@ -292,17 +299,17 @@ struct Cgls {
     int product(int dir) {
         const OpPlan &op = dir ? m->AT : m->A;
         const int64_t nin = dir ? w.ns : w.nv, nout = dir ? w.nv : w.ns;
-        float *in = dir ? w.r : w.p;
-        float *out = dir ? w.s : w.q;
+        T *in = dir ? w.r : w.p;
+        T *out = dir ? w.s : w.q;
         for (int g = 0; g < w.n_mb; ++g) {
-            float *gin = in + (int64_t)g * nin;
+            T *gin = in + (int64_t)g * nin;
             const void *opnd = gin;
             const float *scale = nullptr;
-            if (m->vdt != XCT_F32) {
+            if (m->vdt == XCT_F16 || m->vdt == XCT_BF16) {
                 const int gg = vec_grid(nin);
                 int rc0 = launch_pow2_scale(w.amax + (int64_t)g * w.F, w.F, w.scale, w.inv, st);
                 if (rc0) return rc0;
-                hipLaunchKernelGGL(k_cast16, dim3(gg), dim3(kVecThreads), 0, st, (const float *)gin, nin, w.F,
+                hipLaunchKernelGGL(k_cast16, dim3(gg), dim3(kVecThreads), 0, st, (const float *)(const void *)gin, nin, w.F,
                                    (const float *)w.inv, (uint16_t *)w.op16, (int)m->vdt);
                 XCT_HIP_TRY(hipGetLastError());
                 opnd = w.op16;
@@ -317,59 +324,48 @@ struct Cgls {
     }
 };
 
-}  // namespace xct
-
-using namespace xct;
-
-extern "C" size_t xct_cgls_workspace_bytes(const xct_matrix *m, int batch, int iters) {
-    if (!m || batch < 1 || iters < 0) return 0;
-    return cgls_layout(m, batch, iters, nullptr, nullptr);
-}
-
-extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
-                        void *workspace, double *resid, int32_t *status, void *stream) {
-    if (!m || !y || !x || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
-    if (batch < 1 || iters < 0) return fail(XCT_ERR_INVALID, "batch must be >= 1 and iters >= 0");
-    if (!valid_dtype(y_dtype)) return fail(XCT_ERR_INVALID, "bad y dtype");
-    if (m->vdt == XCT_F64) return fail(XCT_ERR_UNSUPPORTED, "CGLS runs on FP32, FP16 and BF16 matrices");
-    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
-    Cgls c;
+template <class T>
+static int run_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
+                    void *workspace, double *resid, int32_t *status, hipStream_t st) {
+    constexpr bool kF64 = sizeof(T) == 8;
+    Cgls<T> c;
     c.m = m;
-    c.st = (hipStream_t)stream;
-    cgls_layout(m, batch, iters, (char *)workspace, &c.w);
-    CglsWs &w = c.w;
-    hipStream_t st = c.st;
+    c.st = st;
+    cgls_layout<T>(m, batch, iters, (char *)workspace, &c.w);
+    CglsWs<T> &w = c.w;
     const int gv = c.vec_grid(w.nv), gs = c.vec_grid(w.ns);
     int rc;
-    const bool narrow = m->vdt != XCT_F32;  // 16-bit operands: per-slice max of each product's input
+    const bool narrow = m->vdt == XCT_F16 || m->vdt == XCT_BF16;  // 16-bit operands: max of each product's input
     uint32_t *amax = narrow ? w.amax : nullptr;
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, w.amax, (int64_t)w.Bp);
     // r = y ; x = 0 ; yy = |y|^2
     for (int g = 0; g < w.n_mb; ++g) {
-        rc = launch_to_internal(m->sino, y, y_dtype, batch, g * w.F, w.F, w.r + (int64_t)g * w.ns, XCT_F32, nullptr, st);
+        rc = launch_to_internal(m->sino, y, y_dtype, batch, g * w.F, w.F, w.r + (int64_t)g * w.ns,
+                                kF64 ? XCT_F64 : XCT_F32, nullptr, st);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_zero_words, dim3(gv), dim3(kVecThreads), 0, st, (uint32_t *)w.x, w.nv * w.n_mb);
+    hipLaunchKernelGGL(k_zero_words, dim3(gv), dim3(kVecThreads), 0, st, (uint32_t *)w.x,
+                       w.nv * w.n_mb * (int64_t)(sizeof(T) / 4));
     XCT_HIP_TRY(hipGetLastError());
     for (int g = 0; g < w.n_mb; ++g) {
-        hipLaunchKernelGGL(k_sqnorm, dim3(gs), dim3(kVecThreads), 0, st, (const float *)(w.r + (int64_t)g * w.ns), w.ns,
+        hipLaunchKernelGGL(k_sqnorm<T>, dim3(gs), dim3(kVecThreads), 0, st, (const T *)(w.r + (int64_t)g * w.ns), w.ns,
                            w.F, w.dotp + (int64_t)g * kVecBlocks * w.F);
     }
     XCT_HIP_TRY(hipGetLastError());
     if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
     if ((rc = c.scalars(kSetYY, w.resid))) return rc;
     // s = A^T r ; gamma = |s|^2 ; p = s
-    if (narrow && (rc = c.absmax(w.r, w.ns))) return rc;
+    if (narrow && (rc = c.absmax((const float *)(const void *)w.r, w.ns))) return rc;
     if ((rc = c.product(1))) return rc;
     if ((rc = c.scalars(kSetGamma, nullptr))) return rc;
-    XCT_HIP_TRY(hipMemcpyAsync(w.p, w.s, sizeof(float) * w.nv * w.n_mb, hipMemcpyDeviceToDevice, st));
-    if (narrow && (rc = c.absmax(w.p, w.nv))) return rc;
+    XCT_HIP_TRY(hipMemcpyAsync(w.p, w.s, sizeof(T) * w.nv * w.n_mb, hipMemcpyDeviceToDevice, st));
+    if (narrow && (rc = c.absmax((const float *)(const void *)w.p, w.nv))) return rc;
     for (int k = 0; k < iters; ++k) {
         if ((rc = c.product(0))) return rc;  // q = A p, delta
         if ((rc = c.scalars(kSetAlpha, nullptr))) return rc;
         for (int g = 0; g < w.n_mb; ++g)  // r -= alpha q (and |r|^2, max |r|)
-            hipLaunchKernelGGL(k_axpy_res, dim3(gs), dim3(kVecThreads), 0, st, w.r + (int64_t)g * w.ns,
-                               (const float *)(w.q + (int64_t)g * w.ns), w.ns, w.F, (const double *)(w.alpha + g * w.F),
+            hipLaunchKernelGGL(k_axpy_res<T>, dim3(gs), dim3(kVecThreads), 0, st, w.r + (int64_t)g * w.ns,
+                               (const T *)(w.q + (int64_t)g * w.ns), w.ns, w.F, (const double *)(w.alpha + g * w.F),
                                w.dotp + (int64_t)g * kVecBlocks * w.F, amax ? amax + (int64_t)g * w.F : nullptr);
         XCT_HIP_TRY(hipGetLastError());
         if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
@@ -377,14 +373,17 @@ extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, f
         if ((rc = c.product(1))) return rc;  // s = A^T r, gamma'
         if ((rc = c.scalars(kSetBeta, nullptr))) return rc;
         for (int g = 0; g < w.n_mb; ++g)  // x += alpha p ; p = s + beta p (and max |p|)
-            hipLaunchKernelGGL(k_update_xp, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
-                               w.p + (int64_t)g * w.nv, (const float *)(w.s + (int64_t)g * w.nv), w.nv, w.F,
+            hipLaunchKernelGGL(k_update_xp<T>, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
+                               w.p + (int64_t)g * w.nv, (const T *)(w.s + (int64_t)g * w.nv), w.nv, w.F,
                                (const double *)(w.alpha + g * w.F), (const double *)(w.beta + g * w.F),
                                amax ? amax + (int64_t)g * w.F : nullptr);
         XCT_HIP_TRY(hipGetLastError());
     }
     for (int g = 0; g < w.n_mb; ++g) {
-        rc = launch_from_internal(m->vol, w.x + (int64_t)g * w.nv, batch, g * w.F, w.F, x, XCT_F32, st);
+        if constexpr (kF64)
+            rc = launch_from_internal64(m->vol, w.x + (int64_t)g * w.nv, batch, g * w.F, w.F, x, XCT_F32, st);
+        else
+            rc = launch_from_internal(m->vol, w.x + (int64_t)g * w.nv, batch, g * w.F, w.F, x, XCT_F32, st);
         if (rc) return rc;
     }
     // the residual rows (padded batch Bp on the device) and the status words
@@ -396,4 +395,25 @@ extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, f
         XCT_HIP_TRY(hipMemcpyAsync(status, w.stopped, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st));
     if (resid || status) XCT_HIP_TRY(hipStreamSynchronize(st));
     return XCT_OK;
+}
+
+}  // namespace xct
+
+using namespace xct;
+
+extern "C" size_t xct_cgls_workspace_bytes(const xct_matrix *m, int batch, int iters) {
+    if (!m || batch < 1 || iters < 0) return 0;
+    return m->vdt == XCT_F64 ? cgls_layout<double>(m, batch, iters, nullptr, nullptr)
+                             : cgls_layout<float>(m, batch, iters, nullptr, nullptr);
+}
+
+extern "C" int xct_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float *x, int batch, int iters,
+                        void *workspace, double *resid, int32_t *status, void *stream) {
+    if (!m || !y || !x || !workspace) return fail(XCT_ERR_INVALID, "NULL argument");
+    if (batch < 1 || iters < 0) return fail(XCT_ERR_INVALID, "batch must be >= 1 and iters >= 0");
+    if (!valid_dtype(y_dtype)) return fail(XCT_ERR_INVALID, "bad y dtype");
+    if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (m->vdt == XCT_F64) return run_cgls<double>(m, y, y_dtype, x, batch, iters, workspace, resid, status, st);
+    return run_cgls<float>(m, y, y_dtype, x, batch, iters, workspace, resid, status, st);
 }

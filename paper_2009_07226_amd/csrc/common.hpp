@@ -94,7 +94,7 @@ struct xct_matrix {
     int n = 0, M = 0, C = 0;
     xct_dtype vdt = XCT_F32;
     int fuse = 16;
-    int remap = 1;
+    int remap = 0;  // the xcd_remap build option
     xct::Grid vol, sino;
     xct::OpPlan A, AT;
     double build_seconds = 0.0;
@@ -166,6 +166,9 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
                        void *internal, xct_dtype storage, const float *inv_scale, hipStream_t s);
 int launch_from_internal(const Grid &g, const float *internal, int batch, int s0, int F, void *nat,
                          xct_dtype io, hipStream_t s);
+// The same from FP64 internal rows (FP64 matrices).
+int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat,
+                           xct_dtype io, hipStream_t s);
 // From per-slice max |v| bits in amax[F]: scale[f] = m = 2^ceil(log2 max)
 // (1 for zero), inv[f] = 1/m; clears amax for reuse.
 int launch_pow2_scale(uint32_t *amax, int F, float *scale, float *inv, hipStream_t s);

@@ -19,9 +19,10 @@
 //   * ELL entries are grouped four steps per lane so one lane fetches four
 //     (slot, length) pairs with one wide non-temporal load (the matrix is
 //     streamed once per pass and should not evict the vectors from L2/MALL);
-//   * workgroup ids are remapped so that consecutive blocks of the Hilbert
-//     order (which share most of their input footprint) run on one XCD and
-//     share its L2.
+//   * workgroup ids are remapped so that each XCD takes runs of consecutive
+//     blocks of the Hilbert order (which share most of their input
+//     footprint, in its L2) while the eight XCDs advance through the order
+//     together (their staged tiles shared in the memory-side cache).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -140,7 +141,7 @@ struct SpmmArgs {
     const float *scale;
     double *sq_partial;
     int64_t n_row_tiles;
-    int n_blocks, T, remap, lanes;
+    int n_blocks, T, remap, lanes;  // remap: consecutive blocks per XCD chunk (0: plain order)
     int W;  // row tiles per block (R per wavefront)
 };
 
@@ -347,10 +348,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     const int tid = threadIdx.x, nthr = blockDim.x, P = nthr >> 6, W = a.W;
     // wave-uniform: keeps the slab bounds and loop control in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    // Workgroup i runs on XCD i mod 8 (the dispatcher deals workgroups to
+    // the XCDs in turn); its k-th workgroup takes block (chunk * 8 + xcd) * G
+    // + k mod G with chunk = k / G: each XCD works through runs of G
+    // consecutive blocks (sharing their input tiles in its L2) while the
+    // eight XCDs advance through the Hilbert order together (their staged
+    // tiles shared in the memory-side cache).
     int b = blockIdx.x;
-    if (a.remap) {
-        const int per = (a.n_blocks + 7) >> 3;
-        b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (a.remap > 0) {
+        const int G = a.remap, xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+        b = ((k / G) * 8 + xcd) * G + k % G;
     }
     if (b >= a.n_blocks) return;  // whole workgroup, before any barrier
 
@@ -681,6 +688,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
 
 // ---- kernel timing for measurement tools -----------------------------------
 
+// Blocks per XCD run for the launch (see k_spmm): option -1 plain order; 1
+// one contiguous run of the Hilbert order per XCD; n >= 2 runs of n blocks;
+// 0 (default) runs of 4.  Measured (projection + backprojection step):
+// contiguous runs keep an XCD's blocks far from the other XCDs', so the
+// eight staged regions overflow the memory-side cache once a pass stages
+// more than ~128 MB (64 x 2048^2 FP16: 56.8 ms, 128 x 2816^2 FP16: 333 ms);
+// runs of 4 keep the XCDs in one region (52.6 ms, 287 ms; plain order 53.5,
+// 293 ms) and match contiguous runs where the input fits (16 x 1024^2:
+// 4.81 vs 4.82 ms FP32, 3.34 vs 3.38 ms FP16).
+constexpr int kDefaultRun = 4;
+static int remap_chunk(int opt, const OpPlan &op) {
+    if (opt < 0) return 0;
+    if (opt == 1) return (op.n_blocks + 7) / 8;
+    return opt >= 2 ? opt : kDefaultRun;
+}
+
 struct ProfileRec {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
@@ -705,7 +728,7 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     a.n_row_tiles = op.n_row_tiles;
     a.n_blocks = op.n_blocks;
     a.T = op.T;
-    a.remap = L.remap;
+
     a.lanes = op.lanes;
     a.W = op.W;
     typedef typename Stor<FMT>::T XT;
@@ -718,7 +741,8 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
                                         (int)smem));
         attr_bytes = (int)smem;
     }
-    const int grid = L.remap ? ((op.n_blocks + 7) / 8) * 8 : op.n_blocks;
+    a.remap = remap_chunk(L.remap, op);
+    const int grid = a.remap ? 8 * a.remap * ((op.n_blocks + 8 * a.remap - 1) / (8 * a.remap)) : op.n_blocks;
     if (grid == 0) return XCT_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof.on) {
@@ -1066,8 +1090,8 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
 }
 
 // FP64 sums (FP64 matrices) to the natural layout
-static int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat,
-                                  xct_dtype io, hipStream_t st) {
+int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat, xct_dtype io,
+                           hipStream_t st) {
     const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F64);
     const int64_t n = g.n_tiles * kTileSlots;
     const dim3 grid((unsigned)((n + 255) / 256)), blk(256);

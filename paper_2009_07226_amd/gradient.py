@@ -59,7 +59,12 @@ def projected_gradient(A: Matrix, y: torch.Tensor, iters: int, step: Union[float
 
 def opnorm_sq(A: Matrix, iters: int = 30, seed: int = 0) -> float:
     """||A||_2^2 by power iteration on A^T A with the operator pair (a lower
-    bound that tightens with ``iters``)."""
+    bound that tightens with ``iters``).
+
+    A caller-side helper for choosing the step length, not part of the
+    solver: each iteration is one projection and one backprojection through
+    the library; the scalar bookkeeping (two dot products and a scaling per
+    iteration) is done with torch on the device, once per step-length choice."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     v = torch.rand((1,) + A.vol_shape, generator=g, dtype=torch.float32).to(A.device)
     est = 0.0

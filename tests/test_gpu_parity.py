@@ -129,7 +129,8 @@ def test_project_backproject_parity(N, M, C, B):
 
 
 @pytest.mark.parametrize("opts", [dict(stage_order=1), dict(tile_waves=4, lds_bytes=32768),
-                                  dict(tile_waves=16, xcd_remap=-1), dict(fuse=4), dict(fuse=2),
+                                  dict(tile_waves=16, xcd_remap=-1), dict(xcd_remap=1), dict(xcd_remap=3),
+                                  dict(tile_waves=5, xcd_remap=7), dict(fuse=4), dict(fuse=2),
                                   dict(lane_order=1), dict(tile_waves=16, lds_bytes=163840),
                                   dict(slab_order=1), dict(fuse=8), dict(fuse=8, lane_order=1),
                                   dict(tile_waves=32), dict(tile_waves=32, fuse=8), dict(tile_waves=32, fuse=1),
@@ -563,7 +564,31 @@ def test_fp64_limits():
     with pytest.raises(xct.XctError) as e:
         xct.Matrix(16, 12, 16, "f64", fuse=16)
     assert e.value.code == -4
-    A = gpu_matrix(16, 12, 16, "f64")
-    with pytest.raises(xct.XctError) as e:
-        xct.cgls(A, torch.rand(1, 12, 16, device="cuda"), 2)
-    assert e.value.code == -4
+
+
+@pytest.mark.parametrize("N,M,C,B,iters", CGLS_CASES)
+def test_fp64_cgls_every_iteration(N, M, C, B, iters):
+    """CGLS on an FP64 matrix (FP64 vectors, products and scalars; x returned
+    in FP32) against the oracle at every iteration: FP64 rounding is amplified
+    like FP32's (the FP64 envelope, eps = u64 sqrt(L) / 3, grows about
+    tenfold per iteration) but from 1e-16, so up to the fixed count the
+    iterate stays within the FP32 rounding of the returned x (2 u32) plus
+    twice that envelope, where FP32 CGLS deviates by percents."""
+    from cgls_envelope import envelope_history
+    A = gpu_matrix(N, M, C, "f64")
+    Ao, ATo, _, y = cgls_problem(N, M, C, B)
+    yd = y.double().numpy().reshape(B, -1)
+    xg, resg, stg = gpu_cgls_history(A, y.cuda(), iters)
+    xo, reso, sto, xho = oracle.cgls(Ao, ATo, yd, iters, history=True)
+    L = max(Ao.nnz / Ao.shape[0], ATo.nnz / ATo.shape[0])
+    env_x, env_r = envelope_history(Ao, ATo, yd, xho, reso, iters, storage="f64",
+                                    eps=2.0 ** -53 * math.sqrt(L) / 3.0)
+    u32 = 2.0 ** -24
+    for k in range(1, iters + 1):
+        dx = rel_err(xg[k - 1], xho[k - 1])
+        dr = np.abs(resg[k] - reso[k]) / reso[k]
+        banner(f"  f64 cgls N={N} k={k:2d} x dev {dx.max():.2e} (envelope {env_x[k].max():.2e}) "
+               f"resid dev {dr.max():.2e}")
+        assert np.all(dx <= 2 * u32 + 2 * env_x[k]), (k, dx)
+        assert np.all(dr <= 1e-10 + 2 * env_r[k]), (k, dr)
+    assert np.all(stg == sto)
