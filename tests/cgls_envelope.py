@@ -21,8 +21,10 @@ Each run ("order") works on the oracle's matrix (the FP64 chord lengths):
   * solver vectors x, r, p stored in FP32 after every update, step lengths
     rounded to FP32 where they scale a vector, dot products in FP64.
 ``envelope_history(..., storage="f64")`` instead keeps everything in FP64
-and adds a relative perturbation eps * N(0,1) to every product output
-(the amplification study of the oracle pins)."""
+and adds eps * N(0,1) * (|A| |v|)_r to output r of every product A v (the
+forward error of a dot product is proportional to the sum of its terms'
+magnitudes; A is non-negative, so |A| |v| is the product of |v|): the
+amplification study of the oracle pins, and the envelope of FP64 solvers."""
 import ctypes
 import hashlib
 import os
@@ -113,8 +115,8 @@ def envelope_history(A, AT, y, xh_ref, res_ref, iters, storage="f32", seeds=(0, 
     """A, AT: the oracle's CSR pair.  y (B, rows); xh_ref (iters, B, cols):
     the oracle's x_1..x_iters; res_ref (iters+1, B): its residual history.
     storage: "f32", "f16" or "bf16" (the solver's arithmetic above), or
-    "f64" (FP64 throughout, with a relative perturbation eps * N(0,1) of every
-    product output).  Returns (env_x, env_r), each (iters+1, B): max over the
+    "f64" (FP64 throughout, every product output perturbed by eps * N(0,1)
+    * (|A| |v|)_r).  Returns (env_x, env_r), each (iters+1, B): max over the
     seeded runs of ||x_k - x_k*|| / ||x_k*|| and of | r_k - r_k* | / r_k*
     (0 at k = 0, where both start from x = 0)."""
     y = np.asarray(y, np.float64)
@@ -129,10 +131,11 @@ def envelope_history(A, AT, y, xh_ref, res_ref, iters, storage="f32", seeds=(0, 
                 return np.asarray(v, np.float64)
 
             def pA(v):
-                return oracle.spmm(A, v) * (1.0 + eps * rng.standard_normal((v.shape[0], A.shape[0])))
+                return oracle.spmm(A, v) + eps * rng.standard_normal((v.shape[0], A.shape[0])) * oracle.spmm(A, np.abs(v))
 
             def pT(w):
-                return oracle.spmm(AT, w) * (1.0 + eps * rng.standard_normal((w.shape[0], AT.shape[0])))
+                return (oracle.spmm(AT, w) +
+                        eps * rng.standard_normal((w.shape[0], AT.shape[0])) * oracle.spmm(AT, np.abs(w)))
         else:
             vec = f32
             fA, fT = Fp32Product(A, storage, 2 * seed + 1), Fp32Product(AT, storage, 2 * seed + 2)
