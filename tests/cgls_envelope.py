@@ -24,7 +24,10 @@ Each run ("order") works on the oracle's matrix (the FP64 chord lengths):
 and adds eps * N(0,1) * (|A| |v|)_r to output r of every product A v (the
 forward error of a dot product is proportional to the sum of its terms'
 magnitudes; A is non-negative, so |A| |v| is the product of |v|): the
-amplification study of the oracle pins, and the envelope of FP64 solvers."""
+amplification study of the oracle pins, and the envelope of FP64 solvers.
+With ``entry_sd`` every run also adds entry_sd * N(0,1) to each matrix
+entry of A and of A^T (independently): the absolute rounding of chord
+lengths that another FP64 tracer computes from the same geometry."""
 import ctypes
 import hashlib
 import os
@@ -111,12 +114,12 @@ def _pow2_ceil(mx):
     return m
 
 
-def envelope_history(A, AT, y, xh_ref, res_ref, iters, storage="f32", seeds=(0, 1, 2), eps=0.0):
+def envelope_history(A, AT, y, xh_ref, res_ref, iters, storage="f32", seeds=(0, 1, 2), eps=0.0, entry_sd=0.0):
     """A, AT: the oracle's CSR pair.  y (B, rows); xh_ref (iters, B, cols):
     the oracle's x_1..x_iters; res_ref (iters+1, B): its residual history.
     storage: "f32", "f16" or "bf16" (the solver's arithmetic above), or
     "f64" (FP64 throughout, every product output perturbed by eps * N(0,1)
-    * (|A| |v|)_r).  Returns (env_x, env_r), each (iters+1, B): max over the
+    * (|A| |v|)_r, the entries by entry_sd * N(0,1)).  Returns (env_x, env_r), each (iters+1, B): max over the
     seeded runs of ||x_k - x_k*|| / ||x_k*|| and of | r_k - r_k* | / r_k*
     (0 at k = 0, where both start from x = 0)."""
     y = np.asarray(y, np.float64)
@@ -126,15 +129,21 @@ def envelope_history(A, AT, y, xh_ref, res_ref, iters, storage="f32", seeds=(0, 
     for seed in seeds:
         if storage == "f64":
             rng = np.random.default_rng(seed)
+            Ap, ATp = A, AT
+            if entry_sd > 0.0:
+                Ap, ATp = A.copy(), AT.copy()
+                Ap.data = Ap.data + entry_sd * rng.standard_normal(Ap.nnz)
+                ATp.data = ATp.data + entry_sd * rng.standard_normal(ATp.nnz)
 
             def vec(v):
                 return np.asarray(v, np.float64)
 
-            def pA(v):
-                return oracle.spmm(A, v) + eps * rng.standard_normal((v.shape[0], A.shape[0])) * oracle.spmm(A, np.abs(v))
+            def pA(v, Ap=Ap):
+                return (oracle.spmm(Ap, v) +
+                        eps * rng.standard_normal((v.shape[0], A.shape[0])) * oracle.spmm(A, np.abs(v)))
 
-            def pT(w):
-                return (oracle.spmm(AT, w) +
+            def pT(w, ATp=ATp):
+                return (oracle.spmm(ATp, w) +
                         eps * rng.standard_normal((w.shape[0], AT.shape[0])) * oracle.spmm(AT, np.abs(w)))
         else:
             vec = f32

@@ -569,11 +569,17 @@ def test_fp64_limits():
 @pytest.mark.parametrize("N,M,C,B,iters", CGLS_CASES)
 def test_fp64_cgls_every_iteration(N, M, C, B, iters):
     """CGLS on an FP64 matrix (FP64 vectors, products and scalars; x returned
-    in FP32) against the oracle at every iteration: FP64 rounding is amplified
-    like FP32's (the FP64 envelope, eps = u64 sqrt(L) / 3, grows about
-    tenfold per iteration) but from 1e-16, so up to the fixed count the
-    iterate stays within the FP32 rounding of the returned x (2 u32) plus
-    twice that envelope, where FP32 CGLS deviates by percents."""
+    in FP32) against the oracle at every iteration.  FP64 rounding is
+    amplified like FP32's but from 1e-16: the FP64 envelope (16 runs, each
+    with its own perturbation of the sums, eps = u64 sqrt(L) / 3, and of the
+    chord lengths, N(0,1) N u64 per entry: both tracers difference ray or
+    offset parameters of magnitude up to about N, so their lengths carry
+    absolute rounding of that order) grows about tenfold per iteration.  Up
+    to the fixed count the iterate stays within the FP32 rounding of the
+    returned x (2 u32) plus twice that envelope, where FP32 CGLS deviates by
+    percents.  Near the end the oracle's own rounding, amplified, is of the
+    envelope's size, so a slice where it dominates deviates by the same
+    amount in the GPU run and in every envelope run."""
     from cgls_envelope import envelope_history
     A = gpu_matrix(N, M, C, "f64")
     Ao, ATo, _, y = cgls_problem(N, M, C, B)
@@ -581,8 +587,8 @@ def test_fp64_cgls_every_iteration(N, M, C, B, iters):
     xg, resg, stg = gpu_cgls_history(A, y.cuda(), iters)
     xo, reso, sto, xho = oracle.cgls(Ao, ATo, yd, iters, history=True)
     L = max(Ao.nnz / Ao.shape[0], ATo.nnz / ATo.shape[0])
-    env_x, env_r = envelope_history(Ao, ATo, yd, xho, reso, iters, storage="f64",
-                                    eps=2.0 ** -53 * math.sqrt(L) / 3.0)
+    env_x, env_r = envelope_history(Ao, ATo, yd, xho, reso, iters, storage="f64", seeds=range(16),
+                                    eps=2.0 ** -53 * math.sqrt(L) / 3.0, entry_sd=2.0 ** -53 * N)
     u32 = 2.0 ** -24
     for k in range(1, iters + 1):
         dx = rel_err(xg[k - 1], xho[k - 1])
