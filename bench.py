@@ -284,23 +284,38 @@ def cgls_errors_512(oracle, xct, torch, phantoms, dev, iters=30):
 class TracedOracleCgls(threading.Thread):
     """The oracle's CGLS history on a few slices of a scan too large for an
     explicit A and A^T in host memory (A traced into a CSR, A^T applied as its
-    transposed product), run on the host while the GPU measurements go on."""
+    transposed product), run on the host while the GPU measurements go on.
+    The sinogram is the oracle's projection of the phantom slices x (FP64)
+    plus 1% seeded noise, rounded to FP32; ``sinogram()`` waits for it and
+    returns it for the GPU side, so both solve the same problem."""
 
-    def __init__(self, oracle, N, M, C, y, iters, threads):
+    def __init__(self, oracle, phantoms, N, M, C, x, slices, seed, iters, threads):
         super().__init__(daemon=True)
-        self.args = (oracle, N, M, C, y, iters, threads)
-        self.result, self.error, self.seconds = None, None, None
+        self.args = (oracle, phantoms, N, M, C, x, slices, seed, iters, threads)
+        self.result, self.error, self.seconds, self.y = None, None, None, None
+        self._y_ready = threading.Event()
+
+    def sinogram(self):
+        self._y_ready.wait()
+        return self.y
 
     def run(self):
-        oracle, N, M, C, y, iters, threads = self.args
+        import numpy as np
+        oracle, phantoms, N, M, C, x, slices, seed, iters, threads = self.args
         t = time.perf_counter()
         try:
             oracle.set_threads(threads)
             with oracle.TracedA(N, M, C) as T:
-                _, res, _, xh = T.cgls(y, iters, history=True)
+                y = T.project(x)
+                y = y + 0.01 * np.abs(y).max() * phantoms.noise((M * C,), slices, seed)
+                self.y = y.astype(np.float32).astype(np.float64)
+                self._y_ready.set()
+                _, res, _, xh = T.cgls(self.y, iters, history=True)
             self.result = (xh, res)
         except Exception as e:  # reported in the JSON line, never raised from the thread
             self.error = repr(e)
+        finally:
+            self._y_ready.set()
         self.seconds = time.perf_counter() - t
 
 
@@ -570,23 +585,27 @@ def main():
         x4 = phantoms.ellipsoid_phantom(N4, B4, 60, seed=4, device=dev).float()
         c4 = {"workload": f"{B4} slices {N4}x{N4}, {M4} angles over [0,pi), {N4} channels, 60-ellipsoid phantom, "
                           f"1% noise; CGLS {it4} iterations"}
-        y4 = None
+        if oracle is not None:
+            # the oracle's CGLS history on 2 slices, on the host meanwhile
+            x2 = x4[sl4].double().cpu().numpy().reshape(len(sl4), -1)
+            traced = TracedOracleCgls(oracle, phantoms, N4, M4, N4, x2, sl4, 4, 3, max(1, threads - 2))
+            traced.start()
+            del x2
+        y4 = y2 = None
         for dt in ("f32", "f16", "bf16"):
             A4 = xct.Matrix(N4, M4, N4, dt)
             if y4 is None:
                 y4 = xct.project(A4, x4)
                 y4 = (y4 + 0.01 * float(y4.abs().max()) * phantoms.noise_torch((M4, N4), B4, 4, dev)).contiguous()
-                if oracle is not None:
-                    # the oracle's CGLS history on 2 slices, on the host meanwhile
-                    y2 = y4[sl4].double().cpu().numpy().reshape(len(sl4), -1)
-                    traced = TracedOracleCgls(oracle, N4, M4, N4, y2, 3, max(1, threads - 2))
-                    traced.start()
             r = time_products(xct, torch, A4, x4, 3, warmup=1)
             r["cgls_s_per_iter"] = round(cgls_s_per_iter(xct, torch, A4, y4, it4), 6)
             _, res4, _ = xct.cgls(A4, y4, it4)
             r["residual_median_final"] = float(np.median(res4[-1]))
-            if oracle is not None:
-                r["_iterates"] = gpu_cgls_iterates(xct, A4, y4[sl4].contiguous(), 3)
+            if traced is not None:
+                if y2 is None and traced.sinogram() is not None:
+                    y2 = torch.from_numpy(traced.sinogram()).float().reshape(len(sl4), M4, N4).to(dev)
+                if y2 is not None:
+                    r["_iterates"] = gpu_cgls_iterates(xct, A4, y2, 3)
             c4[dt] = r
             log(f"  {dt}: step {r['ms_per_step']:.2f} ms, kernel {100 * r['kernel_frac']:.1f}% of peak, "
                 f"CGLS {1e3 * r['cgls_s_per_iter']:.2f} ms/iter")
@@ -606,7 +625,7 @@ def main():
         c4["fp16_cgls_speedup"] = round(c4["f32"]["cgls_s_per_iter"] / c4["f16"]["cgls_s_per_iter"], 3)
         c4["fp16_fuse32_cgls_speedup"] = round(c4["f32"]["cgls_s_per_iter"] / c4["f16_fuse32"]["cgls_s_per_iter"], 3)
         out["c64x2048"] = c4
-        del x4, y4
+        del x4, y4, y2
         torch.cuda.empty_cache()
 
         # 128 slices 2816^2, 2250 angles, 2816 channels, FP16 (the large single-GPU share)
@@ -650,7 +669,7 @@ def main():
             oracle.set_threads(threads)
             c4 = out["c64x2048"]
             rep = {"slices": sl4, "k": [1, 2, 3], "oracle_seconds": round(traced.seconds, 1)}
-            if traced.result is not None:
+            if traced.result is not None and all("_iterates" in c4[dt] for dt in ("f32", "f16", "bf16")):
                 xho, reso = traced.result
                 for dt in ("f32", "f16", "bf16"):
                     xg, resg = c4[dt].pop("_iterates")
@@ -658,7 +677,7 @@ def main():
                     rep[dt + "_residual_rel_dev_max"] = float((abs(resg - reso) / reso).max())
                 rep["f16_within_1e-3_through_k"] = holds_through(rep["f16"], 1e-3)
             else:
-                rep["error"] = traced.error
+                rep["error"] = traced.error or "no GPU iterates"
                 for dt in ("f32", "f16", "bf16"):
                     c4[dt].pop("_iterates", None)
             c4["cgls_vs_oracle"] = rep

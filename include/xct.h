@@ -95,6 +95,10 @@ typedef struct {
                         accumulation with packed FP16 FMAs (FP16 matrices only; the paper's
                         "half precision" variant, for measurement: sums keep ~11 bits, so
                         results deviate by ~1e-2 relative; a single fused slice keeps FP32) */
+    int debug_poison_lds; /* debug: 1 fills a workgroup's LDS stage buffer with NaN before each
+                             stage is copied in, so that an entry reading a slot its stage did
+                             not stage turns its sums into NaN (tests compare such a build with
+                             a plain one bit for bit); 0 (default) off */
 } xct_build_opts;
 
 /* Statistics of one operator (A or A^T). */

@@ -1149,6 +1149,8 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
     if (o.arith < 0 || o.arith > 1) return fail(XCT_ERR_INVALID, "arith must be 0 or 1");
     if (o.arith == 1 && value_dtype != XCT_F16)
         return fail(XCT_ERR_UNSUPPORTED, "FP16 arithmetic needs an FP16 matrix");
+    if (o.debug_poison_lds < 0 || o.debug_poison_lds > 1)
+        return fail(XCT_ERR_INVALID, "debug_poison_lds must be 0 or 1");
     const int row_bytes = F * elem_bytes(value_dtype);
     const int lanes = o.lane_order;
     // A length that rounds to zero in the stored format contributes nothing
@@ -1204,6 +1206,7 @@ extern "C" int xct_build_matrix(int n, int n_angles, int n_channels, xct_dtype v
         rc = fail(XCT_ERR_INTERNAL, std::string("build: ") + e.what());
     }
     m->A.arith16 = m->AT.arith16 = o.arith == 1 ? 1 : 0;
+    m->A.poison = m->AT.poison = o.debug_poison_lds;
     if (rc) {
         std::string msg = g_last_error;
         xct_free_matrix(m);

@@ -45,6 +45,7 @@ struct OpPlan {
     int W = 0;  // row tiles per block
     int R = 1;  // row tiles per wavefront (W / R wavefronts per block)
     int arith16 = 0;  // FP16 arithmetic (FP16 matrix; measurement variant)
+    int poison = 0;   // debug: NaN-fill the LDS stage buffer before each stage copy
     int T = 0;  // input tiles per stage
     int n_blocks = 0;
     int lanes = 0;  // lane_slot order of the rows within a row tile

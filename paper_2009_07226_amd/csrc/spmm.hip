@@ -44,6 +44,7 @@ __device__ __forceinline__ float h16_to_f32(uint32_t bits) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
 }
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // Storage element of the staged operand.
 template <int FMT> struct Stor;
@@ -234,13 +235,36 @@ __device__ __forceinline__ void use_group(const Group<FMT> &g, const uint32_t (&
         __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the FMAs
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
+            if constexpr (FMT == XCT_BF16 && R::SPC >= 2) {
+                // BF16: one v_dot2c_f32_bf16 per slice takes the packed pair
+                // of operands as stored, against (value, 0) for the even
+                // slice and (0, value) for the odd one: the product of two
+                // BF16 values is exact in FP32, so each step is a single
+                // FP32 rounding of the sum, as with the FMA after widening
+                // (which costs one more instruction per slice).
+                const uint32_t pv = sw[q0 + k];  // slot << 16 | value
+                const bf16x2 vlo = __builtin_bit_cast(bf16x2, pv & 0xffffu);
+                const bf16x2 vhi = __builtin_bit_cast(bf16x2, pv << 16);
 #pragma unroll
-            for (int j = 0; j < R::CH; ++j) {
-                AT x[R::SPC];
-                expand<FMT, R::SPC>(w[k][j], x);
+                for (int j = 0; j < R::CH; ++j) {
+                    const uint32_t u[4] = {w[k][j].x, w[k][j].y, w[k][j].z, w[k][j].w};
 #pragma unroll
-                for (int t = 0; t < R::SPC; ++t)
-                    acc[j * R::SPC + t] = fma_acc(v[q0 + k], x[t], acc[j * R::SPC + t]);
+                    for (int t = 0; t < R::SPC / 2; ++t) {
+                        const bf16x2 x2 = __builtin_bit_cast(bf16x2, u[t]);
+                        float &a0 = acc[j * R::SPC + 2 * t], &a1 = acc[j * R::SPC + 2 * t + 1];
+                        a0 = __builtin_amdgcn_fdot2_f32_bf16(vlo, x2, a0, false);
+                        a1 = __builtin_amdgcn_fdot2_f32_bf16(vhi, x2, a1, false);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < R::CH; ++j) {
+                    AT x[R::SPC];
+                    expand<FMT, R::SPC>(w[k][j], x);
+#pragma unroll
+                    for (int t = 0; t < R::SPC; ++t)
+                        acc[j * R::SPC + t] = fma_acc(v[q0 + k], x[t], acc[j * R::SPC + t]);
+                }
             }
         }
     }
@@ -338,8 +362,9 @@ template <int F> struct ReadBatch<XCT_F64, F, 2> { static constexpr int value = 
 template <> struct ReadBatch<XCT_BF16, 32, 1> { static constexpr int value = 2; };
 
 // RT: row tiles per wavefront (a.W / RT wavefronts per block); H16: FP16
-// arithmetic on an FP16 matrix (F >= 2).
-template <int FMT, int F, int RT, bool H16>
+// arithmetic on an FP16 matrix (F >= 2); POISON: the debug build option that
+// NaN-fills the stage buffer before each stage copy.
+template <int FMT, int F, int RT, bool H16, bool POISON>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spmm(SpmmArgs a) {
     typedef RowShape<FMT, F> R;
     constexpr int D = RingDepth<FMT>::value;
@@ -433,6 +458,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)
     // and goes to the placed row of its slot (rows of 16 bytes or more are
     // placed plainly, so whole tiles land contiguously).
     auto copy_static = [&](int q0, int nt) {
+        if constexpr (POISON) {
+            // debug build option: every byte of the stage buffer NaN (all-ones
+            // is a NaN in each value format) before the stage lands, so that
+            // an entry reading a slot this stage did not stage yields NaN
+            for (int i = tid; i < a.T * kVecPerTile; i += nthr)
+                ((u32x4 *)smem)[i] = u32x4{~0u, ~0u, ~0u, ~0u};
+            __syncthreads();  // the fill is in LDS before any copy writes
+        }
         if constexpr (kDma) {
             // Rows placed plainly: a tile's rows are contiguous in LDS, so each
             // 1 KB piece (64 vectors) is copied straight into LDS with no
@@ -735,11 +768,13 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
     size_t smem = (size_t)op.T * kTileSlots * F * sizeof(XT);
     const size_t red = sizeof(double) * (size_t)op.W * F;
     if (smem < red) smem = red;
-    static int attr_bytes = 0;  // per instantiation: largest dynamic LDS size enabled so far
-    if ((int)smem > attr_bytes) {
-        XCT_HIP_TRY(hipFuncSetAttribute((const void *)k_spmm<FMT, F, RT, H16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)smem));
-        attr_bytes = (int)smem;
+    // the debug build option (NaN-filled stage buffers) has its own instantiation
+    const void *kern = op.poison ? (const void *)k_spmm<FMT, F, RT, H16, true>
+                                 : (const void *)k_spmm<FMT, F, RT, H16, false>;
+    static int attr_bytes[2] = {0, 0};  // per instantiation: largest dynamic LDS size enabled so far
+    if ((int)smem > attr_bytes[op.poison]) {
+        XCT_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        attr_bytes[op.poison] = (int)smem;
     }
     a.remap = remap_chunk(L.remap, op);
     const int grid = a.remap ? 8 * a.remap * ((op.n_blocks + 8 * a.remap - 1) / (8 * a.remap)) : op.n_blocks;
@@ -750,7 +785,10 @@ static int launch_one(const SpmmLaunch &L, hipStream_t st) {
         XCT_HIP_TRY(hipEventCreate(&e1));
         XCT_HIP_TRY(hipEventRecord(e0, st));
     }
-    hipLaunchKernelGGL((k_spmm<FMT, F, RT, H16>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
+    if (op.poison)
+        hipLaunchKernelGGL((k_spmm<FMT, F, RT, H16, true>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
+    else
+        hipLaunchKernelGGL((k_spmm<FMT, F, RT, H16, false>), dim3(grid), dim3(op.W / RT * kTileSlots), smem, st, a);
     XCT_HIP_TRY(hipGetLastError());
     if (g_prof.on) {
         XCT_HIP_TRY(hipEventRecord(e1, st));

@@ -14,13 +14,16 @@ namespace xct {
 
 // Streaming read of a buffer (16-byte non-temporal loads, grid-stride), the
 // reference ceiling for the SpMM's matrix stream.
-static __device__ uint32_t g_probe_sink;  // target of the probe's (practically never taken) store
+// Target of the probe's (practically never taken) store.  The kernel gets
+// its address as an argument: a store to a file-local variable that nothing
+// reads is dead code, and with it every load of the probe.
+static __device__ uint32_t g_probe_sink;
 
 // Eight 16-byte loads in flight per thread (grid-strided), then the tail one
 // at a time: with fewer in flight the probe reads below what the device
 // streams (measured 6.4 TB/s with one, 6.9 TB/s with eight).
 constexpr int kProbeUnroll = 8;
-__global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n) {
+__global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n, uint32_t *sink) {
     uint32_t acc = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,7 +38,7 @@ __global__ void __launch_bounds__(256) k_read_probe(const u32x4 *p, int64_t n) {
         const u32x4 v = __builtin_nontemporal_load(p + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
-    if (acc == 0x9e3779b9u) g_probe_sink = acc;  // keeps the loads; practically never stores
+    if (acc == 0x9e3779b9u) *sink = acc;  // keeps the loads; practically never stores
 }
 
 // Number of elements of v that are NaN or infinite (dt: 0 FP32, 1 FP16,
@@ -61,9 +64,11 @@ __global__ void __launch_bounds__(256) k_count_nonfinite(const void *v, int64_t 
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
-// The probe's two timing events, created once per device.
+// The probe's two timing events and the sink's device address, set up once
+// per device.
 constexpr int kMaxProbeDevices = 64;
 static hipEvent_t g_probe_ev[kMaxProbeDevices][2];
+static uint32_t *g_probe_sink_ptr[kMaxProbeDevices];
 static std::mutex g_probe_mu;
 }  // namespace xct
 
@@ -80,12 +85,14 @@ extern "C" int xct_read_bandwidth(const void *buf, int64_t bytes, int reps, doub
     hipEvent_t *ev = g_probe_ev[dev];
     for (int q = 0; q < 2; ++q)
         if (!ev[q]) XCT_HIP_TRY(hipEventCreate(&ev[q]));
+    if (!g_probe_sink_ptr[dev]) XCT_HIP_TRY(hipGetSymbolAddress((void **)&g_probe_sink_ptr[dev], HIP_SYMBOL(g_probe_sink)));
+    uint32_t *sink = g_probe_sink_ptr[dev];
     const int grid = 16384;
-    hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n);  // warm-up
+    hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n, sink);  // warm-up
     XCT_HIP_TRY(hipGetLastError());
     XCT_HIP_TRY(hipEventRecord(ev[0], st));
     for (int r = 0; r < reps; ++r) {
-        hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n);
+        hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(256), 0, st, (const u32x4 *)buf, n, sink);
         XCT_HIP_TRY(hipGetLastError());
     }
     XCT_HIP_TRY(hipEventRecord(ev[1], st));

@@ -36,7 +36,8 @@ class XctError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("tile_waves", ctypes.c_int), ("fuse", ctypes.c_int), ("lds_bytes", ctypes.c_int),
                 ("xcd_remap", ctypes.c_int), ("stage_order", ctypes.c_int),
-                ("lane_order", ctypes.c_int), ("slab_order", ctypes.c_int), ("arith", ctypes.c_int)]
+                ("lane_order", ctypes.c_int), ("slab_order", ctypes.c_int), ("arith", ctypes.c_int),
+                ("debug_poison_lds", ctypes.c_int)]
 
 
 class OpStats(ctypes.Structure):
@@ -167,14 +168,15 @@ class Matrix:
 
     def __init__(self, n: int, n_angles: int, n_channels: Optional[int] = None, dtype="f32", *,
                  tile_waves: int = 0, fuse: int = 0, lds_bytes: int = 0, xcd_remap: int = 0, stage_order: int = 0,
-                 lane_order: int = 0, slab_order: int = 0, arith: int = 0, stream=None):
+                 lane_order: int = 0, slab_order: int = 0, arith: int = 0, debug_poison_lds: int = 0,
+                 stream=None):
         L = lib()
         n_channels = n if n_channels is None else n_channels
         self.n, self.n_angles, self.n_channels = int(n), int(n_angles), int(n_channels)
         self.value_dtype = _dt(dtype)
         self.device = torch.device("cuda", torch.cuda.current_device())
         opts = BuildOpts(int(tile_waves), int(fuse), int(lds_bytes), int(xcd_remap), int(stage_order),
-                         int(lane_order), int(slab_order), int(arith))
+                         int(lane_order), int(slab_order), int(arith), int(debug_poison_lds))
         h = ctypes.c_void_p()
         _check(L.xct_build_matrix(self.n, self.n_angles, self.n_channels, self.value_dtype, ctypes.byref(opts),
                                   _stream(stream), ctypes.byref(h)))

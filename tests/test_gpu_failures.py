@@ -102,3 +102,12 @@ def test_cgls_nonfinite_slice_is_reported_and_isolated(vdt):
         assert np.array_equal(rb[:, b], rg[:, b])
     assert all(math.isfinite(v) for v in rb[:, 0])
     A.free()
+
+
+def test_read_probe_reads_at_a_physical_rate():
+    """The streaming-read ceiling the bench reports: a probe whose loads the
+    compiler dropped would report far above the device's 8 TB/s."""
+    big = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    g = xct.read_bandwidth(big, reps=3)
+    banner(f"read probe {g:.0f} GB/s over 1 GiB")
+    assert 1000.0 < g < 8000.0, g

@@ -165,9 +165,10 @@ def test_workload_64x2048_cgls_every_iteration_vs_oracle():
     """FP32, FP16 and BF16 CGLS at 2048^2, 1500 angles, 2048 channels against
     the FP64 oracle at every one of the first 3 iterations, on 2 slices of the
     60-ellipsoid phantom with 1% noise (slices are independent, so 2 slices
-    stand for the 64-slice batch; the sinogram is the GPU's FP32 projection
-    plus noise, shared by both sides).  The oracle holds only A (90 GB as a
-    CSR in host memory) and applies A^T as its transposed product.
+    stand for the 64-slice batch).  The oracle holds only A (90 GB as a CSR
+    in host memory) and applies A^T as its transposed product; the sinogram
+    is its projection of the phantom slices plus seeded noise, rounded to
+    FP32 and given to both sides.
 
     Over the first 3 iterations rounding is not yet amplified (the envelope
     studies at 128^2 and 512^2 grow by less than 2x by k = 3), so each format
@@ -178,24 +179,23 @@ def test_workload_64x2048_cgls_every_iteration_vs_oracle():
     sl = [17, 40]
     B = len(sl)
     bars = {"f32": 1e-5, "f16": 1e-3, "bf16": 8e-3}
-    x4 = phantoms.ellipsoid_phantom(N, 64, 60, seed=4, device="cuda").float()
-    gpu = {}
-    y = None
-    for dt in ("f32", "f16", "bf16"):
-        torch.cuda.empty_cache()
-        A = xct.Matrix(N, M, C, dt)
-        if y is None:
-            y = xct.project(A, x4[sl].contiguous())
-            y = (y + 0.01 * float(y.abs().max()) * phantoms.noise_torch((M, C), B, 4, "cuda")).contiguous()
-            del x4
-        gpu[dt] = gpu_iterates(A, y, iters)
-        A.free()
-        del A
-        banner(f"64x2048 per-iteration: GPU CGLS {dt} done")
+    x2 = phantoms.ellipsoid_phantom(N, 64, 60, seed=4, device="cuda")[sl].cpu().numpy().reshape(B, -1)
     torch.cuda.empty_cache()
-    yd = y.double().cpu().numpy().reshape(B, -1)
     with oracle.TracedA(N, M, C) as T:
         banner(f"  oracle A traced: nnz {T.nnz}")
+        y = T.project(x2)
+        y = y + 0.01 * np.abs(y).max() * phantoms.noise((M * C,), sl, 4)
+        yd = y.astype(np.float32).astype(np.float64)
+        yg = torch.from_numpy(yd).float().reshape(B, M, C).cuda()
+        gpu = {}
+        for dt in ("f32", "f16", "bf16"):
+            torch.cuda.empty_cache()
+            A = xct.Matrix(N, M, C, dt)
+            gpu[dt] = gpu_iterates(A, yg, iters)
+            A.free()
+            del A
+            banner(f"64x2048 per-iteration: GPU CGLS {dt} done")
+        torch.cuda.empty_cache()
         xo, reso, sto, xho = T.cgls(yd, iters, history=True)
     banner("  oracle CGLS done")
     for dt in ("f32", "f16", "bf16"):

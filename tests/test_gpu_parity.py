@@ -598,3 +598,28 @@ def test_fp64_cgls_every_iteration(N, M, C, B, iters):
         assert np.all(dx <= 2 * u32 + 2 * env_x[k]), (k, dx)
         assert np.all(dr <= 1e-10 + 2 * env_r[k]), (k, dr)
     assert np.all(stg == sto)
+
+
+@pytest.mark.parametrize("dt,opts,B", [("f32", {}, 5), ("f16", {}, 5), ("bf16", {}, 5), ("f64", {}, 5),
+                                        ("f32", dict(tile_waves=32), 5), ("f16", dict(tile_waves=32), 5),
+                                        ("f16", dict(fuse=32), 33), ("f32", dict(fuse=4, lds_bytes=32768), 5),
+                                        ("f32", dict(fuse=1), 2), ("f16", dict(fuse=2), 3),
+                                        ("f32", dict(stage_order=1), 5), ("f64", dict(fuse=2), 3)])
+def test_lds_poison_build_is_bitwise_equal(dt, opts, B):
+    """The debug build option that fills every stage buffer with NaN before
+    the stage is copied in: if any entry read a slot its stage did not stage
+    (a wrong slot, a tile copied late or into the wrong place, a stage
+    barrier missing), its row would turn NaN.  Both products must equal the
+    plain build's bit for bit."""
+    N, M, C = 64, 90, 64
+    banner(f"lds poison {dt} {opts} B={B}")
+    A0 = gpu_matrix(N, M, C, dt, **opts)
+    A1 = gpu_matrix(N, M, C, dt, debug_poison_lds=1, **opts)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    x = phantoms.ellipse_batch(N, B, 6, seed=77).to(tdt).cuda()
+    y0, y1 = xct.project(A0, x), xct.project(A1, x)
+    assert bool(torch.isfinite(y1).all())
+    assert torch.equal(y0, y1)
+    b0, b1 = xct.backproject(A0, y0), xct.backproject(A1, y0)
+    assert bool(torch.isfinite(b1).all())
+    assert torch.equal(b0, b1)

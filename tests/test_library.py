@@ -74,3 +74,22 @@ def test_workspace_checks_in_the_binding():
         binding._require_workspace(torch.empty(8, 8, dtype=torch.uint8).t(), 1, dev)
     with pytest.raises(TypeError):
         binding._require_workspace(bytearray(64), 1, dev)
+
+
+def _header_struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\}\s*" + name + r"\s*;", text, flags=re.S).group(1)
+    return [(t, f) for t, f in re.findall(r"\b(int|int32_t|int64_t|double)\s+(\w+)\s*;", body)]
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of the header's option and statistics structs have
+    the same fields in the same order and types."""
+    import ctypes as C
+    from paper_2009_07226_amd import xct
+    ctype = {"int": C.c_int, "int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double}
+    for cname, py in (("xct_build_opts", xct.BuildOpts),):
+        want = [(f, ctype[t]) for t, f in _header_struct_fields(cname)]
+        got = [(f, t) for f, t in py._fields_]
+        assert [f for f, _ in got] == [f for f, _ in want], (cname, got, want)
+        assert all(C.sizeof(a) == C.sizeof(b) for (_, a), (_, b) in zip(got, want))
