@@ -339,6 +339,8 @@ def main():
     ap.add_argument("--tile-waves", type=int, default=0)
     ap.add_argument("--lane-order", type=int, default=0)
     ap.add_argument("--slab-order", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=0,
+                    help="workgroup-to-XCD mapping: runs of n blocks (0: default 4), 1 contiguous, -1 plain")
     ap.add_argument("--fuse", type=int, default=0,
                     help="slices fused per matrix pass (1, 2, 4, 8, 16, or 32 for 16-bit matrices; default 16)")
     ap.add_argument("--arith", type=int, default=0,
@@ -377,11 +379,11 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     default_opts = not (args.stage_order or args.lds_bytes or args.tile_waves or args.fuse or args.arith or
-                        args.lane_order or args.slab_order)
+                        args.lane_order or args.slab_order or args.xcd_remap)
 
     log(f"building {args.dtype} matrix N={N} M={M} C={C}")
     opts = dict(stage_order=args.stage_order, lds_bytes=args.lds_bytes, tile_waves=args.tile_waves, fuse=args.fuse,
-                lane_order=args.lane_order, slab_order=args.slab_order)
+                lane_order=args.lane_order, slab_order=args.slab_order, xcd_remap=args.xcd_remap)
     opts16 = dict(opts, arith=args.arith)  # FP16 arithmetic applies to FP16 matrices only
     A = xct.Matrix(N, M, C, args.dtype, **(opts16 if args.dtype == "f16" else opts))
     info = A.info()

@@ -39,10 +39,11 @@ struct CglsWs {
     void *op16 = nullptr;    // one group's 16-bit operand (volume or sinogram sized)
     double *dotp = nullptr;  // [n_mb][kVecBlocks][F]
     double *sqp = nullptr;   // [n_mb][max blocks][F]
-    double *gamma = nullptr, *delta = nullptr, *alpha = nullptr, *beta = nullptr, *yy = nullptr, *sum = nullptr;
+    double *gamma = nullptr, *delta = nullptr, *alpha = nullptr, *beta = nullptr, *yy = nullptr;
     int32_t *stopped = nullptr;
     double *resid = nullptr;  // [iters+1][Bp]
-    uint32_t *amax = nullptr;
+    uint32_t *amax = nullptr;   // per-slice max |r| of the next backprojection's operand
+    uint32_t *amaxp = nullptr;  // per-slice max |p| of the next projection's operand
     float *scale = nullptr, *inv = nullptr;
     int64_t sq_stride = 0;    // max blocks
 };
@@ -75,10 +76,10 @@ static size_t cgls_layout(const xct_matrix *m, int batch, int iters, char *base,
     c.alpha = (double *)take(sizeof(double) * c.Bp);
     c.beta = (double *)take(sizeof(double) * c.Bp);
     c.yy = (double *)take(sizeof(double) * c.Bp);
-    c.sum = (double *)take(sizeof(double) * c.Bp);
     c.stopped = (int32_t *)take(sizeof(int32_t) * c.Bp);
     c.resid = (double *)take(sizeof(double) * (size_t)(iters + 1) * c.Bp);
     c.amax = (uint32_t *)take(sizeof(uint32_t) * (size_t)c.Bp);
+    c.amaxp = (uint32_t *)take(sizeof(uint32_t) * (size_t)c.Bp);
     c.scale = (float *)take(sizeof(float) * kMaxFuse);
     c.inv = (float *)take(sizeof(float) * kMaxFuse);
     if (w) *w = c;
@@ -123,39 +124,125 @@ __device__ __forceinline__ void block_max(float m, int F, uint32_t *amax) {
     }
 }
 
-// r -= alpha q, with block partials of |r|^2 (sinogram) and, when amax is
-// given, the per-slice max |r| (the next product's operand scale)
-template <class T>
-__global__ void k_axpy_res(T *r, const T *q, int64_t n, int F, const double *alpha, double *part, uint32_t *amax) {
-    double acc = 0.0;
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const T a = (T)alpha[i & (F - 1)];
-        const T t = fma(-a, q[i], r[i]);
-        r[i] = t;
-        acc += (double)t * (double)t;
-        m = fmaxf(m, fabsf((float)t));
+// The elementwise kernels read and write V consecutive elements per access
+// (16 bytes: 4 FP32 or 2 FP64 values; V = 1 when F is not a multiple of
+// that).  The grid stride (kVecBlocks * kVecThreads * V elements) is a
+// multiple of F, so a thread's elements always belong to the same V slices
+// f0 .. f0 + V - 1, whose scalars it loads once.
+template <class T> struct Vec16;
+template <> struct Vec16<float> { typedef float t __attribute__((ext_vector_type(4))); static constexpr int V = 4; };
+template <> struct Vec16<double> { typedef double t __attribute__((ext_vector_type(2))); static constexpr int V = 2; };
+template <class T, int V> struct VecOf { typedef typename Vec16<T>::t t; };
+template <class T> struct VecOf<T, 1> { typedef T t; };
+template <int V, class VT, class T>
+__device__ __forceinline__ T lane_of(const VT &v, int k) {
+    if constexpr (V == 1) return v; else return v[k];
+}
+template <int V, class VT, class T>
+__device__ __forceinline__ void set_lane(VT &v, int k, T x) {
+    if constexpr (V == 1) v = x; else v[k] = x;
+}
+
+// Block partial sums per slice of the V running sums of each thread into
+// part[blockIdx.x][F] (element t*V + k of a block's sums belongs to slice
+// (t*V + k) mod F), in a fixed order.
+template <int V>
+__device__ __forceinline__ void block_partial_v(const double (&acc)[V], int F, double *part) {
+    __shared__ double red[kVecThreads * V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) red[threadIdx.x * V + k] = acc[k];
+    __syncthreads();
+    if ((int)threadIdx.x < F) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < kVecThreads * V; t += F) s += red[t];
+        part[(int64_t)blockIdx.x * F + threadIdx.x] = s;
     }
-    block_partial(acc, F, part);
-    if (amax) block_max(m, F, amax);
+}
+
+// Per-slice max of the V running maxima of each thread (non-negative
+// floats: their bits order like the values) into amax.
+template <int V>
+__device__ __forceinline__ void block_max_v(const float (&m)[V], int F, uint32_t *amax) {
+    __shared__ float red[kVecThreads * V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) red[threadIdx.x * V + k] = m[k];
+    __syncthreads();
+    if ((int)threadIdx.x < F) {
+        float mx = 0.f;
+        for (int t = threadIdx.x; t < kVecThreads * V; t += F) mx = fmaxf(mx, red[t]);
+        atomicMax(&amax[threadIdx.x], __float_as_uint(mx));
+    }
+}
+
+// r -= alpha q, with block partials of |r|^2 (sinogram) and, when amax is
+// given, the per-slice max |r| (the next product's operand scale).  n: a
+// multiple of V.
+template <class T, int V>
+__global__ void __launch_bounds__(kVecThreads) k_axpy_res(T *r, const T *q, int64_t n, int F, const double *alpha,
+                                                          double *part, uint32_t *amax) {
+    typedef typename VecOf<T, V>::t VT;
+    const int64_t nv = n / V, stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f0 = (int)((i * V) & (F - 1));
+    T a[V];
+    double acc[V];
+    float m[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        a[k] = (T)alpha[f0 + k];
+        acc[k] = 0.0;
+        m[k] = 0.f;
+    }
+    for (; i < nv; i += stride) {
+        VT rv = ((const VT *)r)[i];
+        const VT qv = ((const VT *)q)[i];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const T t = fma(-a[k], lane_of<V, VT, T>(qv, k), lane_of<V, VT, T>(rv, k));
+            set_lane<V>(rv, k, t);
+            acc[k] += (double)t * (double)t;
+            m[k] = fmaxf(m[k], fabsf((float)t));
+        }
+        ((VT *)r)[i] = rv;
+    }
+    block_partial_v<V>(acc, F, part);
+    if (amax) block_max_v<V>(m, F, amax);
 }
 
 // x += alpha p, then p = s + beta p, in one pass (the iterate's update is
 // deferred to here from the step where alpha is found: p is unchanged in
-// between); when amax is given, also the per-slice max |p| of the new p
-template <class T>
-__global__ void k_update_xp(T *x, T *p, const T *s, int64_t n, int F, const double *alpha, const double *beta,
-                            uint32_t *amax) {
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const T a = (T)alpha[i & (F - 1)], bt = (T)beta[i & (F - 1)];
-        const T pv = p[i];
-        if (a != (T)0) x[i] = fma(a, pv, x[i]);  // a stopped slice keeps its iterate, also if p is not finite
-        const T t = fma(bt, pv, s[i]);
-        p[i] = t;
-        m = fmaxf(m, fabsf((float)t));
+// between); when amax is given, also the per-slice max |p| of the new p.
+// A stopped slice (alpha = 0) keeps its iterate, also if p is not finite.
+template <class T, int V>
+__global__ void __launch_bounds__(kVecThreads) k_update_xp(T *x, T *p, const T *s, int64_t n, int F,
+                                                           const double *alpha, const double *beta, uint32_t *amax) {
+    typedef typename VecOf<T, V>::t VT;
+    const int64_t nv = n / V, stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f0 = (int)((i * V) & (F - 1));
+    T a[V], bt[V];
+    float m[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        a[k] = (T)alpha[f0 + k];
+        bt[k] = (T)beta[f0 + k];
+        m[k] = 0.f;
     }
-    if (amax) block_max(m, F, amax);
+    for (; i < nv; i += stride) {
+        const VT pv = ((const VT *)p)[i], sv = ((const VT *)s)[i];
+        VT xv = ((const VT *)x)[i], np;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const T pk = lane_of<V, VT, T>(pv, k);
+            if (a[k] != (T)0) set_lane<V>(xv, k, fma(a[k], pk, lane_of<V, VT, T>(xv, k)));
+            const T t = fma(bt[k], pk, lane_of<V, VT, T>(sv, k));
+            set_lane<V>(np, k, t);
+            m[k] = fmaxf(m[k], fabsf((float)t));
+        }
+        ((VT *)x)[i] = xv;
+        ((VT *)p)[i] = np;
+    }
+    if (amax) block_max_v<V>(m, F, amax);
 }
 
 // Per-slice max |v| of an internal-layout group vector (the solver's first
@@ -182,42 +269,47 @@ __device__ __forceinline__ uint32_t to16(float v, int fmt) {
     return u >> 16;
 }
 
-// o16 = round16(v * inv[slice])
-__global__ void k_cast16(const float *v, int64_t n, int F, const float *inv, uint16_t *o16, int fmt) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        o16[i] = (uint16_t)to16(v[i] * inv[i & (F - 1)], fmt);
+// o16 = round16(v / m[slice]) with m = pow2_at_least(max |v| of the slice)
+// taken from amax (complete: written by the kernel that produced v); block 0
+// also stores m for the product that scales its sums back, and clears
+// amax_next, the maxima that the product after this one accumulates (the
+// solver alternates two arrays, so no block clears what another still
+// reads).  n: a multiple of V.
+template <int V>
+__global__ void __launch_bounds__(kVecThreads) k_cast16(const float *v, int64_t n, int F, const uint32_t *amax,
+                                                        float *scale, uint32_t *amax_next, uint16_t *o16, int fmt) {
+    typedef typename VecOf<float, V>::t VT;
+    const int64_t nv = n / V, stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f0 = (int)((i * V) & (F - 1));
+    if (blockIdx.x == 0 && (int)threadIdx.x < F) {
+        scale[threadIdx.x] = pow2_at_least(__uint_as_float(amax[threadIdx.x]));
+        amax_next[threadIdx.x] = 0u;
+    }
+    float inv[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) inv[k] = 1.f / pow2_at_least(__uint_as_float(amax[f0 + k]));  // exact
+    for (; i < nv; i += stride) {
+        const VT x = ((const VT *)v)[i];
+        if constexpr (V == 4) {
+            const uint32_t h0 = to16(x[0] * inv[0], fmt) | (to16(x[1] * inv[1], fmt) << 16);
+            const uint32_t h1 = to16(x[2] * inv[2], fmt) | (to16(x[3] * inv[3], fmt) << 16);
+            ((uint2 *)o16)[i] = make_uint2(h0, h1);
+        } else {
+            o16[i] = (uint16_t)to16(x * inv[0], fmt);
+        }
+    }
 }
 
 // ---- per-slice scalar updates --------------------------------------------------
 
-// sum[b] = sum over blocks of part[m][blk][f], b = m*F + f: one workgroup per
-// slice, thread t adding blocks t, t + 256, ... in order, then a fixed
-// pairwise tree in LDS, so the result is the same on every run.
 constexpr int kReduceThreads = 256;
-__global__ void __launch_bounds__(kReduceThreads) k_reduce(const double *part, int64_t stride, int nblk, int F,
-                                                           double *sum) {
-    __shared__ double red[kReduceThreads];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int m = b / F, f = b % F;
-    const double *p = part + (int64_t)m * stride * F;
-    double s = 0.0;
-    for (int k = t; k < nblk; k += kReduceThreads) s += p[(int64_t)k * F + f];
-    red[t] = s;
-    __syncthreads();
-    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
-    if (t == 0) sum[b] = red[0];
-}
 
 enum { kSetGamma = 0, kSetAlpha = 1, kSetBeta = 2, kSetYY = 3, kSetResid = 4 };
 
-__global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, double *delta, double *alpha,
-                          double *beta, double *yy, int32_t *stopped, double *resid_row) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= Bp) return;
-    const double v = sum[b];
+// The per-slice scalar update of `mode` for slice b from its new sum v.
+__device__ __forceinline__ void scalar_update(int mode, int b, double v, double *gamma, double *delta, double *alpha,
+                                              double *beta, double *yy, int32_t *stopped, double *resid_row) {
     switch (mode) {
         case kSetYY:
             // a slice whose sinogram holds a non-finite value is not solved
@@ -256,6 +348,29 @@ __global__ void k_scalars(int mode, int Bp, const double *sum, double *gamma, do
     }
 }
 
+// The sum over blocks of part[m][blk][f] for slice b = m*F + f (one
+// workgroup per slice: thread t adds blocks t, t + 256, ... in order, then a
+// fixed pairwise tree in LDS, so the result is the same on every run), then
+// the slice's scalar update.
+__global__ void __launch_bounds__(kReduceThreads) k_reduce_scalars(const double *part, int64_t stride, int nblk, int F,
+                                                                   int mode, double *gamma, double *delta,
+                                                                   double *alpha, double *beta, double *yy,
+                                                                   int32_t *stopped, double *resid_row) {
+    __shared__ double red[kReduceThreads];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int m = b / F, f = b % F;
+    const double *p = part + (int64_t)m * stride * F;
+    double s = 0.0;
+    for (int k = t; k < nblk; k += kReduceThreads) s += p[(int64_t)k * F + f];
+    red[t] = s;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) scalar_update(mode, b, red[0], gamma, delta, alpha, beta, yy, stopped, resid_row);
+}
+
 // ---- orchestration -----------------------------------------------------------
 
 template <class T>
@@ -263,40 +378,73 @@ struct Cgls {
     const xct_matrix *m;
     CglsWs<T> w;
     hipStream_t st;
-    int grid_v, grid_s;
 
     int vec_grid(int64_t n) const {
         return (int)std::max<int64_t>(1, std::min<int64_t>(kVecBlocks, (n + kVecThreads - 1) / kVecThreads));
     }
+    // elements per access of the elementwise kernels for this group size
+    int vec_width() const { return w.F % Vec16<T>::V == 0 ? Vec16<T>::V : 1; }
 
-    int scalars(int mode, double *resid_row) {
-        hipLaunchKernelGGL(k_scalars, dim3((w.Bp + 255) / 256), dim3(256), 0, st, mode, w.Bp, (const double *)w.sum,
+    // Per-slice sums of the partials, then the scalar update `mode`.
+    int reduce_scalars(const double *part, int64_t stride, int nblk, int mode, double *resid_row) {
+        hipLaunchKernelGGL(k_reduce_scalars, dim3(w.Bp), dim3(kReduceThreads), 0, st, part, stride, nblk, w.F, mode,
                            w.gamma, w.delta, w.alpha, w.beta, w.yy, w.stopped, resid_row);
-        XCT_HIP_TRY(hipGetLastError());
-        return XCT_OK;
-    }
-
-    int reduce(const double *part, int64_t stride, int nblk) {
-        hipLaunchKernelGGL(k_reduce, dim3(w.Bp), dim3(kReduceThreads), 0, st, part, stride, nblk, w.F, w.sum);
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
     }
 
     // Per-slice max |v| of every group of an operand vector into amax (the
     // solver's first operands; the updates produce it for later ones).
-    int absmax(const float *v, int64_t n) {
+    int absmax(const float *v, int64_t n, uint32_t *amax) {
         for (int g = 0; g < w.n_mb; ++g)
             hipLaunchKernelGGL(k_absmax_int, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, v + (int64_t)g * n, n, w.F,
-                               w.amax + (int64_t)g * w.F);
+                               amax + (int64_t)g * w.F);
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
+
+    int axpy_res(uint32_t *amax) {  // r -= alpha q (and |r|^2, max |r|)
+        const int gs = vec_grid(w.ns);
+        for (int g = 0; g < w.n_mb; ++g) {
+            T *r = w.r + (int64_t)g * w.ns;
+            const T *q = w.q + (int64_t)g * w.ns;
+            const double *al = w.alpha + g * w.F;
+            double *part = w.dotp + (int64_t)g * kVecBlocks * w.F;
+            uint32_t *am = amax ? amax + (int64_t)g * w.F : nullptr;
+            if (vec_width() > 1)
+                hipLaunchKernelGGL((k_axpy_res<T, Vec16<T>::V>), dim3(gs), dim3(kVecThreads), 0, st, r, q, w.ns, w.F, al,
+                                   part, am);
+            else
+                hipLaunchKernelGGL((k_axpy_res<T, 1>), dim3(gs), dim3(kVecThreads), 0, st, r, q, w.ns, w.F, al, part, am);
+        }
+        XCT_HIP_TRY(hipGetLastError());
+        return XCT_OK;
+    }
+
+    int update_xp(uint32_t *amax) {  // x += alpha p ; p = s + beta p (and max |p|)
+        const int gv = vec_grid(w.nv);
+        for (int g = 0; g < w.n_mb; ++g) {
+            T *x = w.x + (int64_t)g * w.nv, *p = w.p + (int64_t)g * w.nv;
+            const T *s = w.s + (int64_t)g * w.nv;
+            const double *al = w.alpha + g * w.F, *be = w.beta + g * w.F;
+            uint32_t *am = amax ? amax + (int64_t)g * w.F : nullptr;
+            if (vec_width() > 1)
+                hipLaunchKernelGGL((k_update_xp<T, Vec16<T>::V>), dim3(gv), dim3(kVecThreads), 0, st, x, p, s, w.nv, w.F,
+                                   al, be, am);
+            else
+                hipLaunchKernelGGL((k_update_xp<T, 1>), dim3(gv), dim3(kVecThreads), 0, st, x, p, s, w.nv, w.F, al, be,
+                                   am);
+        }
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
     }
 
     // One product (dir 0: q = A p, dir 1: s = A^T r) for every group, with
-    // the per-block squared-output partials, then their per-slice sums.  With
-    // a 16-bit matrix, amax holds the operand's per-slice max |v| (cleared
-    // here once read).
-    int product(int dir) {
+    // the per-block squared-output partials, then their per-slice sums and
+    // the scalar update `mode`.  With a 16-bit matrix, amax holds the
+    // operand's per-slice max |v| and amax_next (the other array) is
+    // cleared for the update that follows the product.
+    int product(int dir, int mode, uint32_t *amax, uint32_t *amax_next) {
         const OpPlan &op = dir ? m->AT : m->A;
         const int64_t nin = dir ? w.ns : w.nv, nout = dir ? w.nv : w.ns;
         T *in = dir ? w.r : w.p;
@@ -307,10 +455,15 @@ struct Cgls {
             const float *scale = nullptr;
             if (m->vdt == XCT_F16 || m->vdt == XCT_BF16) {
                 const int gg = vec_grid(nin);
-                int rc0 = launch_pow2_scale(w.amax + (int64_t)g * w.F, w.F, w.scale, w.inv, st);
-                if (rc0) return rc0;
-                hipLaunchKernelGGL(k_cast16, dim3(gg), dim3(kVecThreads), 0, st, (const float *)(const void *)gin, nin, w.F,
-                                   (const float *)w.inv, (uint16_t *)w.op16, (int)m->vdt);
+                const float *vin = (const float *)(const void *)gin;
+                const uint32_t *am = amax + (int64_t)g * w.F;
+                uint32_t *amn = amax_next + (int64_t)g * w.F;
+                if (vec_width() > 1)
+                    hipLaunchKernelGGL(k_cast16<4>, dim3(gg), dim3(kVecThreads), 0, st, vin, nin, w.F, am, w.scale, amn,
+                                       (uint16_t *)w.op16, (int)m->vdt);
+                else
+                    hipLaunchKernelGGL(k_cast16<1>, dim3(gg), dim3(kVecThreads), 0, st, vin, nin, w.F, am, w.scale, amn,
+                                       (uint16_t *)w.op16, (int)m->vdt);
                 XCT_HIP_TRY(hipGetLastError());
                 opnd = w.op16;
                 scale = w.scale;
@@ -320,7 +473,7 @@ struct Cgls {
             int rc = launch_spmm(L, st);
             if (rc) return rc;
         }
-        return reduce(w.sqp, w.sq_stride, op.n_blocks);
+        return reduce_scalars(w.sqp, w.sq_stride, op.n_blocks, mode, nullptr);
     }
 };
 
@@ -335,9 +488,12 @@ static int run_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float
     CglsWs<T> &w = c.w;
     const int gv = c.vec_grid(w.nv), gs = c.vec_grid(w.ns);
     int rc;
-    const bool narrow = m->vdt == XCT_F16 || m->vdt == XCT_BF16;  // 16-bit operands: max of each product's input
-    uint32_t *amax = narrow ? w.amax : nullptr;
+    // 16-bit operands: the per-slice max of each product's input, r's in
+    // amax and p's in amaxp (each product's cast clears the other array)
+    const bool narrow = m->vdt == XCT_F16 || m->vdt == XCT_BF16;
+    uint32_t *amr = narrow ? w.amax : nullptr, *amp = narrow ? w.amaxp : nullptr;
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, w.amax, (int64_t)w.Bp);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, w.amaxp, (int64_t)w.Bp);
     // r = y ; x = 0 ; yy = |y|^2
     for (int g = 0; g < w.n_mb; ++g) {
         rc = launch_to_internal(m->sino, y, y_dtype, batch, g * w.F, w.F, w.r + (int64_t)g * w.ns,
@@ -352,32 +508,18 @@ static int run_cgls(const xct_matrix *m, const void *y, xct_dtype y_dtype, float
                            w.F, w.dotp + (int64_t)g * kVecBlocks * w.F);
     }
     XCT_HIP_TRY(hipGetLastError());
-    if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
-    if ((rc = c.scalars(kSetYY, w.resid))) return rc;
+    if ((rc = c.reduce_scalars(w.dotp, kVecBlocks, gs, kSetYY, w.resid))) return rc;
     // s = A^T r ; gamma = |s|^2 ; p = s
-    if (narrow && (rc = c.absmax((const float *)(const void *)w.r, w.ns))) return rc;
-    if ((rc = c.product(1))) return rc;
-    if ((rc = c.scalars(kSetGamma, nullptr))) return rc;
+    if (narrow && (rc = c.absmax((const float *)(const void *)w.r, w.ns, amr))) return rc;
+    if ((rc = c.product(1, kSetGamma, amr, amp))) return rc;
     XCT_HIP_TRY(hipMemcpyAsync(w.p, w.s, sizeof(T) * w.nv * w.n_mb, hipMemcpyDeviceToDevice, st));
-    if (narrow && (rc = c.absmax((const float *)(const void *)w.p, w.nv))) return rc;
+    if (narrow && (rc = c.absmax((const float *)(const void *)w.p, w.nv, amp))) return rc;
     for (int k = 0; k < iters; ++k) {
-        if ((rc = c.product(0))) return rc;  // q = A p, delta
-        if ((rc = c.scalars(kSetAlpha, nullptr))) return rc;
-        for (int g = 0; g < w.n_mb; ++g)  // r -= alpha q (and |r|^2, max |r|)
-            hipLaunchKernelGGL(k_axpy_res<T>, dim3(gs), dim3(kVecThreads), 0, st, w.r + (int64_t)g * w.ns,
-                               (const T *)(w.q + (int64_t)g * w.ns), w.ns, w.F, (const double *)(w.alpha + g * w.F),
-                               w.dotp + (int64_t)g * kVecBlocks * w.F, amax ? amax + (int64_t)g * w.F : nullptr);
-        XCT_HIP_TRY(hipGetLastError());
-        if ((rc = c.reduce(w.dotp, kVecBlocks, gs))) return rc;
-        if ((rc = c.scalars(kSetResid, w.resid + (int64_t)(k + 1) * w.Bp))) return rc;
-        if ((rc = c.product(1))) return rc;  // s = A^T r, gamma'
-        if ((rc = c.scalars(kSetBeta, nullptr))) return rc;
-        for (int g = 0; g < w.n_mb; ++g)  // x += alpha p ; p = s + beta p (and max |p|)
-            hipLaunchKernelGGL(k_update_xp<T>, dim3(gv), dim3(kVecThreads), 0, st, w.x + (int64_t)g * w.nv,
-                               w.p + (int64_t)g * w.nv, (const T *)(w.s + (int64_t)g * w.nv), w.nv, w.F,
-                               (const double *)(w.alpha + g * w.F), (const double *)(w.beta + g * w.F),
-                               amax ? amax + (int64_t)g * w.F : nullptr);
-        XCT_HIP_TRY(hipGetLastError());
+        if ((rc = c.product(0, kSetAlpha, amp, amr))) return rc;  // q = A p, delta, alpha
+        if ((rc = c.axpy_res(amr))) return rc;                     // r -= alpha q, |r|^2, max |r|
+        if ((rc = c.reduce_scalars(w.dotp, kVecBlocks, gs, kSetResid, w.resid + (int64_t)(k + 1) * w.Bp))) return rc;
+        if ((rc = c.product(1, kSetBeta, amr, amp))) return rc;  // s = A^T r, gamma', beta
+        if ((rc = c.update_xp(amp))) return rc;                  // x += alpha p ; p = s + beta p, max |p|
     }
     for (int g = 0; g < w.n_mb; ++g) {
         if constexpr (kF64)

@@ -173,6 +173,17 @@ int launch_from_internal64(const Grid &g, const double *internal, int batch, int
 // From per-slice max |v| bits in amax[F]: scale[f] = m = 2^ceil(log2 max)
 // (1 for zero), inv[f] = 1/m; clears amax for reuse.
 int launch_pow2_scale(uint32_t *amax, int F, float *scale, float *inv, hipStream_t s);
+// The normalisation of a 16-bit operand with max |v| = mx: the smallest power
+// of two m >= mx (1 for zero or a non-finite max), so v / m lies in [-1, 1].
+__device__ __forceinline__ float pow2_at_least(float mx) {
+    float m = 1.f;
+    if (mx > 0.f && mx <= 3.0e38f) {
+        int e;
+        const float mant = frexpf(mx, &e);  // mx = mant * 2^e, mant in [0.5, 1)
+        m = ldexpf(1.f, mant == 0.5f ? e - 1 : e);
+    }
+    return m;
+}
 // Per-slice max |v| of a natural-layout group, accumulated as float bits into
 // amax[F] (zero on entry), then launch_pow2_scale.
 int launch_natural_scale(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F,

@@ -1070,14 +1070,8 @@ __global__ void k_clear_amax(uint32_t *amax, int n) {
 __global__ void k_pow2_scale(uint32_t *amax, int F, float *scale, float *inv) {
     const int f = threadIdx.x;
     if (f >= F) return;
-    const float mx = __uint_as_float(amax[f]);
+    const float m = pow2_at_least(__uint_as_float(amax[f]));
     amax[f] = 0u;
-    float m = 1.f;
-    if (mx > 0.f && mx <= 3.0e38f) {
-        int e;
-        const float mant = frexpf(mx, &e);  // mx = mant * 2^e, mant in [0.5, 1)
-        m = ldexpf(1.f, mant == 0.5f ? e - 1 : e);
-    }
     scale[f] = m;
     inv[f] = 1.f / m;  // exact: m is a power of two
 }

@@ -113,17 +113,72 @@ def trace_table(stats_csv, out_md, command, workload, note=""):
         fh.write("\n".join(lines) + "\n")
 
 
+SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT")
+
+
+def _last_json(path):
+    for line in reversed(open(path).read().splitlines()):
+        if line.startswith("{"):
+            return json.loads(line)
+    raise ValueError(f"no JSON line in {path}")
+
+
+def sq_table(runs, out_md, command, workload, note=""):
+    """Markdown table of SQ counters of the first projection (A) and
+    backprojection (A^T) launch of each run.  runs: (label, counter csv,
+    bench output holding the JSON line with padded_A / padded_AT); the
+    per-group columns divide by the launch's 4-step groups of 64 lanes."""
+    lines = [f"# SpMM shader counters (rocprofv3 --pmc, SQ block): {workload}", "", "Command:", "", "```", command,
+             "```", "", "Counter values are summed over the device for one launch of A (projection) and one of A^T "
+             "(backprojection); the last two columns divide by the launch's 4-step groups (padded entries / 256).",
+             "", "| Matrix | Launch | " + " | ".join(SQ_COUNTERS) + " | LDS cycles / LDS instr | conflict cycles / "
+             "LDS instr | VALU / group | LDS instr / group |", "|---" * (len(SQ_COUNTERS) + 6) + "|"]
+    for label, csv_path, bench_out in runs:
+        rows = [r for r in csv.DictReader(open(csv_path)) if "k_spmm" in r["Kernel_Name"]]
+        order = []
+        vals = defaultdict(dict)
+        for r in rows:
+            d = int(r["Dispatch_Id"])
+            if d not in vals:
+                order.append(d)
+            vals[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        order.sort()
+        b = _last_json(bench_out)
+        for which, d, padded in (("A", order[0], b["padded_A"]), ("A^T", order[1], b["padded_AT"])):
+            v = vals[d]
+            groups = padded / 256.0
+            lds = v["SQ_INSTS_LDS"]
+            lines.append(f"| {label} | {which} | " + " | ".join(f"{v[c]:.4g}" for c in SQ_COUNTERS) +
+                         f" | {v['SQ_LDS_IDX_ACTIVE'] / lds:.2f} | {v['SQ_LDS_BANK_CONFLICT'] / lds:.3f} | "
+                         f"{v['SQ_INSTS_VALU'] / groups:.1f} | {lds / groups:.1f} |")
+    if note:
+        lines += ["", note]
+    lines += ["", f"Kernel sources SHA-256 (code without comments): `{kernel_sources_sha()}`"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_csv")
     ap.add_argument("write_csv", nargs="?")
     ap.add_argument("out_prefix", nargs="?")
     ap.add_argument("--trace", action="store_true", help="fetch_csv is a kernel_stats.csv, write_csv the output .md")
+    ap.add_argument("--sq", action="append", default=[], metavar="LABEL=CSV,BENCH_OUT",
+                    help="SQ counter table instead (repeat per matrix dtype); fetch_csv is then the output .md")
     ap.add_argument("--note", default="")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
     a = ap.parse_args()
+    if a.sq:
+        runs = []
+        for spec in a.sq:
+            label, rest = spec.split("=", 1)
+            csv_path, bench_out = rest.split(",", 1)
+            runs.append((label, csv_path, bench_out))
+        sq_table(runs, a.fetch_csv, a.command, a.workload, a.note)
+        return
     if a.trace:
         trace_table(a.fetch_csv, a.write_csv, a.command, a.workload, a.note)
         return
