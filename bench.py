@@ -240,7 +240,8 @@ def cpu_baseline(oracle, N, M, C, B, x_host, ys, bytes_step, budget_s, threads):
 
 def headline_errors(oracle, xct, torch, A, N, M, C, x, y, slices, seed=7, n=512):
     """Relative L2 (max over the listed slices) of the headline products on
-    sampled outputs: rays of A x and voxels of A^T y (y the GPU projection)."""
+    sampled outputs: rays of A x (y the GPU projection of x) and voxels of
+    A^T w for a seeded uniform random sinogram w."""
     import numpy as np
     rng = np.random.default_rng(seed)
     rows = rng.choice(M * C, n, replace=False)
@@ -249,12 +250,14 @@ def headline_errors(oracle, xct, torch, A, N, M, C, x, y, slices, seed=7, n=512)
     ref = oracle.project_rows(N, M, C, xs, rows)
     got = y[slices].reshape(len(slices), -1)[:, torch.from_numpy(rows).to(y.device)].double().cpu().numpy()
     e_p = float(rel_l2_rows(got, ref).max())
-    xb = xct.backproject(A, y)
-    ref = oracle.backproject_voxels(N, M, C, y[slices].double().cpu().numpy(), vox)
+    w = torch.rand(y.shape, generator=torch.Generator().manual_seed(seed), dtype=torch.float32)
+    xb = xct.backproject(A, w.to(y.device))
+    ref = oracle.backproject_voxels(N, M, C, w[slices].double().numpy(), vox)
     got = xb[slices].reshape(len(slices), -1)[:, torch.from_numpy(vox).to(y.device)].double().cpu().numpy()
     e_b = float(rel_l2_rows(got, ref).max())
     return {"projection_rel_l2": e_p, "backprojection_rel_l2": e_b, "slices": list(slices),
-            "samples": f"{n} random rays of A x and {n} random voxels of A^T (A x), traced by the oracle"}
+            "samples": f"{n} random rays of A x and {n} random voxels of A^T w (w: seeded uniform sinogram), "
+                       "traced by the oracle"}
 
 
 def cgls_errors_512(oracle, xct, torch, phantoms, dev, iters=30):

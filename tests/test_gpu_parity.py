@@ -140,10 +140,12 @@ def test_plan_options_keep_parity(opts):
     A = gpu_matrix(N, M, C, **opts)
     Ao, ATo = oracle_mats(N, M, C)
     x = phantoms.ellipse_batch(N, B, 6, seed=21).float()
+    y_ref = oracle.project(Ao, x.double().numpy().reshape(B, -1))
     y = xct.project(A, x.cuda()).cpu()
-    assert rel_err(y.numpy(), oracle.project(Ao, x.double().numpy().reshape(B, -1))).max() <= 1e-5
-    xb = xct.backproject(A, y.cuda()).cpu()
-    assert rel_err(xb.numpy(), oracle.backproject(ATo, y.double().numpy())).max() <= 1e-5
+    assert rel_err(y.numpy(), y_ref).max() <= 1e-5
+    yin = torch.from_numpy(y_ref).float().reshape(B, M, C)  # the oracle's sinogram, as FP32 input
+    xb = xct.backproject(A, yin.cuda()).cpu()
+    assert rel_err(xb.numpy(), oracle.backproject(ATo, yin.double().numpy())).max() <= 1e-5
 
 
 @pytest.mark.parametrize("dt,kw,expect", [("f32", {}, True), ("f16", {}, True), ("bf16", {}, True),
@@ -228,8 +230,9 @@ def test_fuse32_parity(dt, tol, N, M, C):
         y_ref = oracle.project(Ao, x.double().numpy().reshape(B, -1))
         y = xct.project(A, x.cuda())
         e = rel_err(y.cpu().numpy(), y_ref)
-        xb = xct.backproject(A, y)
-        eb = rel_err(xb.cpu().numpy(), oracle.backproject(ATo, y.double().cpu().numpy()))
+        yin = torch.from_numpy(y_ref).float().reshape(B, M, C)  # the oracle's sinogram, as FP32 input
+        xb = xct.backproject(A, yin.cuda())
+        eb = rel_err(xb.cpu().numpy(), oracle.backproject(ATo, yin.double().numpy()))
         banner(f"fuse 32 {dt} N={N} B={B}: projection {e.max():.2e} backprojection {eb.max():.2e}")
         assert e.max() <= tol and eb.max() <= tol
 
