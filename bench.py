@@ -260,6 +260,29 @@ def headline_errors(oracle, xct, torch, A, N, M, C, x, y, slices, seed=7, n=512)
                        "traced by the oracle"}
 
 
+def product_errors(oracle, xct, torch, A, x, slices, seed=11, n=256):
+    """Sampled errors of one matrix's products on the listed slices of x (the
+    timed batch): n random rays of A x and n random voxels of A^T w (w a
+    seeded uniform sinogram), each traced by the oracle."""
+    import numpy as np
+    N, M, C = A.n, A.n_angles, A.n_channels
+    xs = x[slices].contiguous()
+    w = torch.rand((len(slices), M, C), generator=torch.Generator().manual_seed(seed), dtype=torch.float32)
+    y = xct.project(A, xs)
+    xb = xct.backproject(A, w.to(x.device).to(x.dtype))
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(M * C, n, replace=False)
+    vox = rng.choice(N * N, n, replace=False)
+    ref = oracle.project_rows(N, M, C, xs.double().cpu().numpy().reshape(len(slices), -1), rows)
+    got = y.reshape(len(slices), -1)[:, torch.from_numpy(rows).to(y.device)].double().cpu().numpy()
+    e_p = float(rel_l2_rows(got, ref).max())
+    ref = oracle.backproject_voxels(N, M, C, w.double().numpy(), vox)
+    got = xb.reshape(len(slices), -1)[:, torch.from_numpy(vox).to(xb.device)].double().cpu().numpy()
+    e_b = float(rel_l2_rows(got, ref).max())
+    return {"projection_rel_l2": round(e_p, 9), "backprojection_rel_l2": round(e_b, 9), "slices": list(slices),
+            "samples": n}
+
+
 def cgls_errors_512(oracle, xct, torch, phantoms, dev, iters=30):
     """CGLS iterates of the three storage formats against the oracle's, every
     iteration, on 2 slices of 512^2 x 360 (1% noise)."""
@@ -532,6 +555,8 @@ def main():
         s16 = time_products(xct, torch, A16, x, args.steps)
         out["fp16_step"] = {k: s16[k] for k in ("ms_per_step", "GBps", "kernel_GBps", "kernel_frac", "launch_ms",
                                                  "padded_A", "padded_AT")}
+        if oracle is not None:
+            out["fp16_step"]["oracle_error"] = product_errors(oracle, xct, torch, A16, x, [0, 15])
         # convergence against time: median relative residual over the slices
         # after k iterations, reached at k * s/iter
         out["cgls"] = {"iters": it, "fp32_s_per_iter": round(t32, 6), "fp16_s_per_iter": round(t16, 6),
@@ -603,6 +628,8 @@ def main():
                 y4 = xct.project(A4, x4)
                 y4 = (y4 + 0.01 * float(y4.abs().max()) * phantoms.noise_torch((M4, N4), B4, 4, dev)).contiguous()
             r = time_products(xct, torch, A4, x4, 3, warmup=1)
+            if oracle is not None:
+                r["oracle_error"] = product_errors(oracle, xct, torch, A4, x4, sl4)
             r["cgls_s_per_iter"] = round(cgls_s_per_iter(xct, torch, A4, y4, it4), 6)
             _, res4, _ = xct.cgls(A4, y4, it4)
             r["residual_median_final"] = float(np.median(res4[-1]))
@@ -620,6 +647,8 @@ def main():
         # FP16 with 32 slices per matrix pass: half the matrix passes of the batch
         A4 = xct.Matrix(N4, M4, N4, "f16", fuse=32)
         r = time_products(xct, torch, A4, x4, 3, warmup=1)
+        if oracle is not None:
+            r["oracle_error"] = product_errors(oracle, xct, torch, A4, x4, sl4)
         r["cgls_s_per_iter"] = round(cgls_s_per_iter(xct, torch, A4, y4, it4), 6)
         c4["f16_fuse32"] = r
         log(f"  f16, 32 fused slices: step {r['ms_per_step']:.2f} ms, kernel {100 * r['kernel_frac']:.1f}% of peak, "
@@ -639,6 +668,8 @@ def main():
         A5 = xct.Matrix(N5, M5, N5, "f16")
         x5 = phantoms.ellipsoid_phantom(N5, B5, 200, seed=5, device=dev, texture=0.05).float()
         r = time_products(xct, torch, A5, x5, 2, warmup=1)
+        if oracle is not None:
+            r["oracle_error"] = product_errors(oracle, xct, torch, A5, x5, [3, 100])
         y5 = xct.project(A5, x5)
         y5 = (y5 + 0.01 * float(y5.abs().max()) * phantoms.noise_torch((M5, N5), B5, 5, dev)).contiguous()
         del x5
@@ -654,6 +685,8 @@ def main():
         A5 = xct.Matrix(N5, M5, N5, "f16", fuse=32)
         x5 = phantoms.ellipsoid_phantom(N5, B5, 200, seed=5, device=dev, texture=0.05).float()
         r = time_products(xct, torch, A5, x5, 2, warmup=1)
+        if oracle is not None:
+            r["oracle_error"] = product_errors(oracle, xct, torch, A5, x5, [3, 100])
         del x5
         r["cgls_20_s"] = round(cgls_seconds(xct, torch, A5, y5, it5, reps=1), 4)
         r["cgls_s_per_iter"] = round((r["cgls_20_s"] - cgls_seconds(xct, torch, A5, y5, 0, reps=1)) / it5, 6)
