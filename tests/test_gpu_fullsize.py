@@ -127,13 +127,26 @@ def test_fp16_matrix_decodes_at_16x1024_1500():
     A.free()
 
 
-@pytest.mark.parametrize("dt,tol", [("f32", 1e-5), ("f16", 2e-3)])
-def test_workload_64x2048_1500(dt, tol):
+@pytest.mark.parametrize("dt,tol,fuse", [("f32", 1e-5, 0), ("f16", 2e-3, 0), ("bf16", 1.5e-2, 0), ("f16", 2e-3, 32)])
+def test_workload_64x2048_1500(dt, tol, fuse):
     N, M, C, B = 2048, 1500, 2048, 64
-    A = xct.Matrix(N, M, C, dt)
+    A = xct.Matrix(N, M, C, dt, fuse=fuse)
     x = phantoms.ellipsoid_phantom(N, B, 60, seed=4, device="cuda").float()
     check_sampled(A, N, M, C, x, [0, 33, 63], tol, seed=4, n_rows=128, n_vox=128)
     del A
+    torch.cuda.empty_cache()
+
+
+def test_fp64_matrix_at_16x1024_1500():
+    """The double-precision variant at the benchmark's size, in its default
+    launch configuration (8 fused slices): sampled rays and voxels of FP64
+    products against the oracle within 1e-12."""
+    N, M, C, B = 1024, 1500, 1024, 16
+    A = xct.Matrix(N, M, C, "f64")
+    assert A.info()["fuse"] == 8
+    x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device="cuda")  # FP64
+    check_sampled(A, N, M, C, x, [0, 7, 15], 1e-12, seed=2, n_rows=128, n_vox=128)
+    A.free()
     torch.cuda.empty_cache()
 
 
