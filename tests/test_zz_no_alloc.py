@@ -18,7 +18,7 @@ def noalloc(A, which, src, out):
     L.xct_apply_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_void_p]
     L.xct_apply_noalloc.restype = ctypes.c_int
-    io = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}[src.dtype]
+    io = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2, torch.float64: 3}[src.dtype]
     rc = L.xct_apply_noalloc(A.handle, which, src.data_ptr(), out.data_ptr(), src.shape[0], io,
                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     if rc != 0:
@@ -26,11 +26,15 @@ def noalloc(A, which, src, out):
     return out
 
 
-@pytest.mark.parametrize("dt,io", [("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.float32)])
-def test_noalloc_equals_workspace_products(dt, io):
+@pytest.mark.parametrize("dt,io,kw,batches", [("f32", torch.float32, {}, (17, 3)),
+                                              ("f16", torch.float16, {}, (17, 3)),
+                                              ("bf16", torch.float32, {}, (17, 3)),
+                                              ("f64", torch.float64, {}, (17, 3)),
+                                              ("f16", torch.float32, {"fuse": 32}, (40, 5))])
+def test_noalloc_equals_workspace_products(dt, io, kw, batches):
     from paper_2009_07226_amd import phantoms
-    A = xct.Matrix(128, 180, 128, dt)
-    for B in (17, 3):  # the second call's input is smaller
+    A = xct.Matrix(128, 180, 128, dt, **kw)
+    for B in batches:  # the second call's input is smaller
         x = phantoms.ellipse_batch(128, B, 6, seed=B).to("cuda", io)
         y_ref = xct.project(A, x)
         y = noalloc(A, 0, x, torch.full_like(y_ref, float("nan")))
