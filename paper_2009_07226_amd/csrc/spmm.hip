@@ -347,14 +347,18 @@ __device__ __forceinline__ void prio_for_remaining(int rem) {
 // stage-by-stage loop (16-bit matrices) every pass reloads all D slots, so a
 // stage whose group count is not a multiple of D re-reads some groups: D = 3
 // or 4 measured fastest (2, 6 and 8 slower).  The flat loop (FP32) reloads a
-// slot only once consumed: D = 4 measured best there (2: +2%, 3: +0.3%).
+// slot only once consumed: D = 5 with the LDS reads of two steps issued
+// together (F = 16) measured best there (D = 4 with whole-group reads: +0.7%
+// at 16 x 1024^2, +1.4% at 64 x 2048^2; D = 6 spills registers).
 template <int FMT> struct RingDepth { static constexpr int value = 4; };
-template <> struct RingDepth<XCT_F32> { static constexpr int value = 4; };
+template <> struct RingDepth<XCT_F32> { static constexpr int value = 5; };
 template <> struct RingDepth<XCT_F64> { static constexpr int value = 3; };  // 10 registers a group
 
-// LDS reads issued together: the whole group, or half of it when a
-// wavefront holds two FP32 accumulator sets of 16 slices (register budget).
+// LDS reads issued together: the whole group, or half of it where the
+// registers are needed elsewhere (the deeper FP32 ring, two FP32 accumulator
+// sets of 16 slices, 32 slices, FP64 rows).
 template <int FMT, int F, int RT> struct ReadBatch { static constexpr int value = 4; };
+template <> struct ReadBatch<XCT_F32, 16, 1> { static constexpr int value = 2; };
 template <> struct ReadBatch<XCT_F32, 16, 2> { static constexpr int value = 2; };
 template <> struct ReadBatch<XCT_F16, 32, 1> { static constexpr int value = 2; };
 template <int F> struct ReadBatch<XCT_F64, F, 1> { static constexpr int value = 2; };
