@@ -280,3 +280,26 @@ def test_large_share_128x2816_2250_fp16():
     cgls_properties(A, y, 20, x_true)
     del A
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f16"])
+def test_lds_poison_at_16x1024_1500(dt):
+    """The NaN-filled stage buffers (debug build option) at the benchmark's
+    size and launch configuration, where every block runs about 20 stages of
+    40 (FP32) or 80 (FP16) tiles: both products equal the plain build's bit
+    for bit, so no entry reads a slot that its stage did not stage."""
+    N, M, C, B = 1024, 1500, 1024, 16
+    x = phantoms.ellipsoid_phantom(N, B, 40, seed=2, device="cuda").float()
+    w = torch.rand((B, M, C), generator=torch.Generator(device="cuda").manual_seed(3), device="cuda")
+    out = []
+    for poison in (0, 1):
+        A = xct.Matrix(N, M, C, dt, debug_poison_lds=poison)
+        out.append((xct.project(A, x), xct.backproject(A, w)))
+        torch.cuda.synchronize()
+        A.free()
+        del A
+        torch.cuda.empty_cache()
+    (y0, b0), (y1, b1) = out
+    banner(f"poisoned stages at 1024^2 {dt}: finite {bool(torch.isfinite(y1).all())}")
+    assert bool(torch.isfinite(y1).all()) and bool(torch.isfinite(b1).all())
+    assert torch.equal(y0, y1) and torch.equal(b0, b1)
