@@ -295,8 +295,9 @@ size_t xct_pgrad_workspace_bytes(const xct_matrix *A, int batch);
  *   lam, eps   lam >= 0, eps > 0
  *   workspace  device, >= xct_pgrad_workspace_bytes(A, batch) bytes, 256-B aligned
  * Each iteration is one projection and one backprojection (the operands of
- * a 16-bit matrix are max-norm scaled and rounded as in xct_project), a
- * residual pass and one fused TV / step / clamp pass.  Enqueued on
+ * a 16-bit matrix are max-norm scaled and rounded as in xct_project), the
+ * residual A x - y taken as the projection is written out (a pass of its
+ * own for FP64 matrices) and one fused TV / step / clamp pass.  Enqueued on
  * `stream`; no host sync.  Errors: XCT_ERR_INVALID, XCT_ERR_HIP.
  */
 int xct_projected_gradient(const xct_matrix *A, const float *y, float *x, int batch, int iters,

@@ -156,6 +156,10 @@ int launch_spmm(const SpmmLaunch &L, hipStream_t s);
 // spmm_workspace(m, batch) bytes, 256-byte aligned.
 int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io, void *workspace,
               void *stream);
+// r = A x - y for FP32 slices in natural layout (the projection, with the
+// subtraction done as its sums are written out); FP32 / 16-bit matrices.
+int spmm_residual(const xct_matrix *m, const float *x, const float *y, float *r, int batch, void *workspace,
+                  hipStream_t st);
 size_t spmm_workspace(const xct_matrix *m, int batch);
 
 // Natural <-> internal layout conversion for one fused group.
@@ -165,8 +169,10 @@ size_t spmm_workspace(const xct_matrix *m, int batch);
 //   memory `inv_scale` [F]; values for slices >= batch are zero.
 int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F,
                        void *internal, xct_dtype storage, const float *inv_scale, hipStream_t s);
+//   from_internal: with `sub` (natural layout like nat, io FP32), writes
+//   the values minus sub.
 int launch_from_internal(const Grid &g, const float *internal, int batch, int s0, int F, void *nat,
-                         xct_dtype io, hipStream_t s);
+                         xct_dtype io, hipStream_t s, const float *sub = nullptr);
 // The same from FP64 internal rows (FP64 matrices).
 int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat,
                            xct_dtype io, hipStream_t s);

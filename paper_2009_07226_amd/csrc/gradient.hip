@@ -150,10 +150,16 @@ extern "C" int xct_projected_gradient(const xct_matrix *m, const float *y, float
     if (nblocks > INT32_MAX) return fail(XCT_ERR_INVALID, "batch too large for one call");
     float *cur = x, *nxt = w.xalt;
     for (int k = 0; k < iters; ++k) {
-        int rc = spmm_call(m, 0, cur, w.q, batch, XCT_F32, w.spmm, stream);
-        if (rc != XCT_OK) return rc;
-        hipLaunchKernelGGL(k_residual, dim3(grid_for(n_sino)), dim3(256), 0, st, w.q, y, n_sino);
-        XCT_HIP_TRY(hipGetLastError());
+        int rc;
+        if (m->vdt == XCT_F64) {  // r = A x, then r -= y
+            rc = spmm_call(m, 0, cur, w.q, batch, XCT_F32, w.spmm, stream);
+            if (rc != XCT_OK) return rc;
+            hipLaunchKernelGGL(k_residual, dim3(grid_for(n_sino)), dim3(256), 0, st, w.q, y, n_sino);
+            XCT_HIP_TRY(hipGetLastError());
+        } else {  // r = A x - y as the projection is written out
+            rc = spmm_residual(m, cur, y, w.q, batch, w.spmm, st);
+            if (rc != XCT_OK) return rc;
+        }
         rc = spmm_call(m, 1, w.q, w.s, batch, XCT_F32, w.spmm, stream);
         if (rc != XCT_OK) return rc;
         hipLaunchKernelGGL(k_pg_update, dim3((unsigned)nblocks), dim3(256), 0, st, cur, w.s, nxt, step, m->n, nseg,

@@ -884,6 +884,7 @@ struct ConvArgs {
     int H, Wd, TW;
     int batch, s0, F;
     int io, storage;
+    const float *sub;  // from_internal: natural-layout FP32 values to subtract, or null
 };
 
 // Natural [B][H][Wd] <-> internal [tile][64][F].  One thread per slot: the F
@@ -1041,7 +1042,8 @@ __global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int s = c.s0 + f;
-        if (s < c.batch) store_io(nat, (int64_t)s * plane + pix, v[f], c.io);
+        const int64_t i = (int64_t)s * plane + pix;
+        if (s < c.batch) store_io(nat, i, c.sub ? v[f] - c.sub[i] : v[f], c.io);
     }
 }
 
@@ -1092,6 +1094,7 @@ static ConvArgs conv_args(const Grid &g, int batch, int s0, int F, int io, int s
     c.F = F;
     c.io = io;
     c.storage = storage;
+    c.sub = nullptr;
     return c;
 }
 
@@ -1143,8 +1146,9 @@ int launch_from_internal64(const Grid &g, const double *internal, int batch, int
 }
 
 int launch_from_internal(const Grid &g, const float *internal, int batch, int s0, int F, void *nat, xct_dtype io,
-                         hipStream_t st) {
-    const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F32);
+                         hipStream_t st, const float *sub) {
+    ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F32);
+    c.sub = sub;
     const int64_t n = g.n_tiles * kTileSlots;
     const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
     switch (F) {
@@ -1213,7 +1217,7 @@ static size_t spmm_ws_layout(const xct_matrix *m, int batch, char *base, SpmmWs 
 // two up to the matrix's fuse: the plan's stages fit the LDS at any smaller
 // F) and a workspace of spmm_ws_layout_f(m, F) bytes.
 static int spmm_call_f(const xct_matrix *m, int dir, const void *src, void *dst, int batch, xct_dtype io,
-                       void *workspace, int F, hipStream_t st) {
+                       void *workspace, int F, hipStream_t st, const float *sub = nullptr) {
     const OpPlan &op = dir ? m->AT : m->A;
     const Grid &gin = dir ? m->sino : m->vol;
     const Grid &gout = dir ? m->vol : m->sino;
@@ -1236,7 +1240,7 @@ static int spmm_call_f(const xct_matrix *m, int dir, const void *src, void *dst,
         rc = launch_spmm(L, st);
         if (rc) return rc;
         rc = m->vdt == XCT_F64 ? launch_from_internal64(gout, (const double *)w.out, batch, s0, F, dst, io, st)
-                               : launch_from_internal(gout, (const float *)w.out, batch, s0, F, dst, io, st);
+                               : launch_from_internal(gout, (const float *)w.out, batch, s0, F, dst, io, st, sub);
         if (rc) return rc;
     }
     return XCT_OK;
@@ -1249,6 +1253,12 @@ int spmm_call(const xct_matrix *m, int dir, const void *src, void *dst, int batc
     if (!valid_dtype(io)) return fail(XCT_ERR_INVALID, "bad io dtype");
     if (((uintptr_t)workspace & 255) != 0) return fail(XCT_ERR_INVALID, "workspace must be 256-byte aligned");
     return spmm_call_f(m, dir, src, dst, batch, io, workspace, run_fuse(batch, m->fuse), (hipStream_t)stream);
+}
+
+int spmm_residual(const xct_matrix *m, const float *x, const float *y, float *r, int batch, void *workspace,
+                  hipStream_t st) {
+    if (m->vdt == XCT_F64) return fail(XCT_ERR_INTERNAL, "the fused residual takes FP32 or 16-bit matrices");
+    return spmm_call_f(m, 0, x, r, batch, XCT_F32, workspace, run_fuse(batch, m->fuse), st, y);
 }
 
 // ---- the allocation-free form of the products --------------------------------
