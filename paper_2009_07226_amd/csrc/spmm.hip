@@ -879,27 +879,52 @@ __device__ __forceinline__ void store_io(void *p, int64_t i, float v, int io) {
 }
 
 struct ConvArgs {
-    const int32_t *coord_of;
-    int64_t n_tiles;
-    int H, Wd, TW;
+    const int32_t *rank_of;  // raster tile -> Hilbert rank
+    int H, Wd, TH, TW;
+    int strips;  // runs of kConvTiles tiles per tile row
     int batch, s0, F;
     int io, storage;
     const float *sub;  // from_internal: natural-layout FP32 values to subtract, or null
 };
 
 // Natural [B][H][Wd] <-> internal [tile][64][F].  One thread per slot: the F
-// loads (or stores) of the natural side are issued together (coalesced over
-// the 8 x 8 tile of a wavefront), the internal side is one contiguous row
-// written (or read) with 16-byte accesses.
+// loads (or stores) of the natural side are issued together, the internal
+// side is one contiguous row written (or read) with 16-byte accesses.  A
+// workgroup of 256 threads takes kConvTiles = 4 horizontally adjacent tiles
+// (8 rows x 32 columns), each wavefront two of its rows, so that a natural
+// access of a wavefront is two whole 128-byte row pieces and its internal
+// rows are four runs of 16 consecutive slots (1 KB each at 16 FP32 slices).
+constexpr int kConvTiles = 4;
+__device__ __forceinline__ bool conv_slot(const ConvArgs &c, int64_t &t, int &row, int &col) {
+    const int b = blockIdx.x;
+    const int ty = b / c.strips, sx = b - ty * c.strips;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = 2 * w + (l >> 5), cs = l & 31;
+    const int tx = sx * kConvTiles + (cs >> 3), cc = cs & 7;
+    if (ty >= c.TH || tx >= c.TW) return false;
+    t = (int64_t)c.rank_of[ty * c.TW + tx] * kTileSlots + r * kTile + cc;
+    row = ty * kTile + r;
+    col = tx * kTile + cc;
+    return true;
+}
+// Rows of 16 bytes or more go through LDS: each thread puts its row there,
+// then the workgroup writes (or, the other way, reads) the internal rows of
+// its tiles as consecutive 16-byte pieces, every wavefront access one
+// contiguous run.  Row r of the workgroup's LDS rows (stride RB + 16 bytes)
+// belongs to thread r; conv_src gives the thread holding slot o of tile
+// tile of the workgroup.
+__device__ __forceinline__ int conv_src(int tile, int o) {
+    const int r = o >> 3;
+    return (r >> 1) * 64 + ((r & 1) << 5) + (tile << 3) + (o & 7);
+}
+inline size_t conv_lds_bytes(int row_bytes) { return row_bytes >= 16 ? (size_t)256 * (row_bytes + 16) : 0; }
+
 template <int F>
 __global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const float *inv) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= c.n_tiles * kTileSlots) return;
-    const int64_t rank = t >> 6;
-    const int o = (int)(t & 63);
-    const int coord = c.coord_of[rank];
-    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
-    const bool in = row < c.H && col < c.Wd;
+    int64_t t = 0;
+    int row = 0, col = 0;
+    const bool valid = conv_slot(c, t, row, col);
+    const bool in = valid && row < c.H && col < c.Wd;
     const int64_t plane = (int64_t)c.H * c.Wd;
     const int64_t pix = (int64_t)row * c.Wd + col;
     float v[F];
@@ -912,34 +937,55 @@ __global__ void k_to_internal(ConvArgs c, const void *nat, void *internal, const
 #pragma unroll
         for (int f = 0; f < F; ++f) v[f] *= inv[f];
     }
-    if (c.storage == XCT_F32) {
-        float *dst = (float *)internal + t * F;
-        if constexpr (F >= 4) {
+    const bool f32 = c.storage == XCT_F32;
+    // the row as 32-bit words (FP32 values or pairs of 16-bit ones)
+    constexpr int NW = F;  // enough for either form
+    uint32_t wd[NW];
+    int nw;
+    if (f32) {
 #pragma unroll
-            for (int q = 0; q < F / 4; ++q) ((f32x4 *)dst)[q] = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-        } else {
-#pragma unroll
-            for (int f = 0; f < F; ++f) dst[f] = v[f];
-        }
+        for (int f = 0; f < F; ++f) wd[f] = __float_as_uint(v[f]);
+        nw = F;
     } else {
         uint16_t h[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) h[f] = (uint16_t)(c.storage == XCT_F16 ? f32_to_h16(v[f]) : f32_to_bf16(v[f]));
-        uint16_t *dst = (uint16_t *)internal + t * F;
-        if constexpr (F >= 8) {
 #pragma unroll
-            for (int q = 0; q < F / 8; ++q) {
-                u32x4 w;
-                w.x = h[8 * q] | ((uint32_t)h[8 * q + 1] << 16);
-                w.y = h[8 * q + 2] | ((uint32_t)h[8 * q + 3] << 16);
-                w.z = h[8 * q + 4] | ((uint32_t)h[8 * q + 5] << 16);
-                w.w = h[8 * q + 6] | ((uint32_t)h[8 * q + 7] << 16);
-                ((u32x4 *)dst)[q] = w;
-            }
+        for (int f = 0; f < F; f += 2) wd[f / 2] = h[f] | (F > 1 ? ((uint32_t)h[f + 1 < F ? f + 1 : f] << 16) : 0u);
+        nw = (F + 1) / 2;
+    }
+    const int RB = f32 ? F * 4 : F * 2;
+    if (RB < 16) {  // narrow rows: written directly
+        if (!valid) return;
+        if (f32) {
+            float *dst = (float *)internal + t * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) dst[f] = v[f];
         } else {
+            uint16_t *dst = (uint16_t *)internal + t * F;
 #pragma unroll
-            for (int f = 0; f < F; ++f) dst[f] = h[f];
+            for (int f = 0; f < F; ++f) dst[f] = (uint16_t)((f & 1) ? (wd[f / 2] >> 16) : (wd[f / 2] & 0xffffu));
         }
+        return;
+    }
+    extern __shared__ __align__(16) char cbuf[];
+    const int RBp = RB + 16;
+    {
+        char *mine = cbuf + (size_t)threadIdx.x * RBp;
+#pragma unroll
+        for (int q = 0; q < NW / 4; ++q)
+            if (4 * q < nw) *(u32x4 *)(mine + 16 * q) = u32x4{wd[4 * q], wd[4 * q + 1], wd[4 * q + 2], wd[4 * q + 3]};
+    }
+    __syncthreads();
+    const int cpr = RB / 16, per_tile = kTileSlots * cpr;
+    const int ty = blockIdx.x / c.strips, sx = blockIdx.x - ty * c.strips;
+    for (int k = threadIdx.x; k < kConvTiles * per_tile; k += blockDim.x) {
+        const int tile = k / per_tile, rem = k - tile * per_tile, o = rem / cpr, q = rem - o * cpr;
+        const int tx = sx * kConvTiles + tile;
+        if (tx >= c.TW) continue;
+        const u32x4 w = *(const u32x4 *)(cbuf + (size_t)conv_src(tile, o) * RBp + 16 * q);
+        const int64_t rank = c.rank_of[ty * c.TW + tx];
+        *(u32x4 *)((char *)internal + (rank * kTileSlots + o) * RB + 16 * q) = w;
     }
 }
 
@@ -959,12 +1005,9 @@ __device__ __forceinline__ void store_io64(void *p, int64_t i, double v, int io)
 
 template <int F>
 __global__ void k_to_internal64(ConvArgs c, const void *nat, double *internal) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= c.n_tiles * kTileSlots) return;
-    const int64_t rank = t >> 6;
-    const int o = (int)(t & 63);
-    const int coord = c.coord_of[rank];
-    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    int64_t t;
+    int row, col;
+    if (!conv_slot(c, t, row, col)) return;
     const bool in = row < c.H && col < c.Wd;
     const int64_t plane = (int64_t)c.H * c.Wd;
     const int64_t pix = (int64_t)row * c.Wd + col;
@@ -985,12 +1028,9 @@ __global__ void k_to_internal64(ConvArgs c, const void *nat, double *internal) {
 
 template <int F>
 __global__ void k_from_internal64(ConvArgs c, const double *internal, void *nat) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= c.n_tiles * kTileSlots) return;
-    const int64_t rank = t >> 6;
-    const int o = (int)(t & 63);
-    const int coord = c.coord_of[rank];
-    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
+    int64_t t;
+    int row, col;
+    if (!conv_slot(c, t, row, col)) return;
     if (row >= c.H || col >= c.Wd) return;
     const int64_t plane = (int64_t)c.H * c.Wd;
     const int64_t pix = (int64_t)row * c.Wd + col;
@@ -1015,30 +1055,45 @@ __global__ void k_from_internal64(ConvArgs c, const double *internal, void *nat)
 
 template <int F>
 __global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= c.n_tiles * kTileSlots) return;
-    const int64_t rank = t >> 6;
-    const int o = (int)(t & 63);
-    const int coord = c.coord_of[rank];
-    const int row = (coord / c.TW) * kTile + (o >> 3), col = (coord % c.TW) * kTile + (o & 7);
-    if (row >= c.H || col >= c.Wd) return;
-    const int64_t plane = (int64_t)c.H * c.Wd;
-    const int64_t pix = (int64_t)row * c.Wd + col;
+    int64_t t = 0;
+    int row = 0, col = 0;
+    const bool valid = conv_slot(c, t, row, col);
     float v[F];
-    const float *src = internal + t * F;
-    if constexpr (F >= 4) {
+    constexpr int RB = F * 4;
+    if constexpr (RB >= 16) {
+        // the workgroup's internal rows into LDS as consecutive 16-byte
+        // pieces, then each thread takes its own row
+        extern __shared__ __align__(16) char cbuf[];
+        constexpr int RBp = RB + 16, cpr = RB / 16, per_tile = kTileSlots * cpr;
+        const int ty = blockIdx.x / c.strips, sx = blockIdx.x - ty * c.strips;
+        for (int k = threadIdx.x; k < kConvTiles * per_tile; k += blockDim.x) {
+            const int tile = k / per_tile, rem = k - tile * per_tile, o = rem / cpr, q = rem - o * cpr;
+            const int tx = sx * kConvTiles + tile;
+            if (tx >= c.TW) continue;
+            const int64_t rank = c.rank_of[ty * c.TW + tx];
+            *(u32x4 *)(cbuf + (size_t)conv_src(tile, o) * RBp + 16 * q) =
+                *(const u32x4 *)((const char *)internal + (rank * kTileSlots + o) * RB + 16 * q);
+        }
+        __syncthreads();
+        if (!valid) return;
+        const char *mine = cbuf + (size_t)threadIdx.x * RBp;
 #pragma unroll
         for (int q = 0; q < F / 4; ++q) {
-            const f32x4 w = ((const f32x4 *)src)[q];
-            v[4 * q] = w.x;
-            v[4 * q + 1] = w.y;
-            v[4 * q + 2] = w.z;
-            v[4 * q + 3] = w.w;
+            const u32x4 w = *(const u32x4 *)(mine + 16 * q);
+            v[4 * q] = __uint_as_float(w.x);
+            v[4 * q + 1] = __uint_as_float(w.y);
+            v[4 * q + 2] = __uint_as_float(w.z);
+            v[4 * q + 3] = __uint_as_float(w.w);
         }
     } else {
+        if (!valid) return;
+        const float *src = internal + t * F;
 #pragma unroll
         for (int f = 0; f < F; ++f) v[f] = src[f];
     }
+    if (row >= c.H || col >= c.Wd) return;
+    const int64_t plane = (int64_t)c.H * c.Wd;
+    const int64_t pix = (int64_t)row * c.Wd + col;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         const int s = c.s0 + f;
@@ -1084,11 +1139,12 @@ __global__ void k_pow2_scale(uint32_t *amax, int F, float *scale, float *inv) {
 
 static ConvArgs conv_args(const Grid &g, int batch, int s0, int F, int io, int storage) {
     ConvArgs c;
-    c.coord_of = g.coord_of;
-    c.n_tiles = g.n_tiles;
+    c.rank_of = g.rank_of;
     c.H = g.H;
     c.Wd = g.Wd;
+    c.TH = g.TH;
     c.TW = g.TW;
+    c.strips = (g.TW + kConvTiles - 1) / kConvTiles;
     c.batch = batch;
     c.s0 = s0;
     c.F = F;
@@ -1101,8 +1157,7 @@ static ConvArgs conv_args(const Grid &g, int batch, int s0, int F, int io, int s
 int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F, void *internal,
                        xct_dtype storage, const float *inv_scale, hipStream_t st) {
     const ConvArgs c = conv_args(g, batch, s0, F, io, storage);
-    const int64_t n = g.n_tiles * kTileSlots;
-    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    const dim3 grid((unsigned)((int64_t)g.TH * c.strips)), blk(256);
     if (storage == XCT_F64) {
         double *d = (double *)internal;
         switch (F) {
@@ -1115,13 +1170,14 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
         XCT_HIP_TRY(hipGetLastError());
         return XCT_OK;
     }
+    const size_t sm = conv_lds_bytes(F * (storage == XCT_F32 ? 4 : 2));
     switch (F) {
-        case 1: hipLaunchKernelGGL(k_to_internal<1>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
-        case 2: hipLaunchKernelGGL(k_to_internal<2>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
-        case 4: hipLaunchKernelGGL(k_to_internal<4>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
-        case 8: hipLaunchKernelGGL(k_to_internal<8>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
-        case 16: hipLaunchKernelGGL(k_to_internal<16>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
-        case 32: hipLaunchKernelGGL(k_to_internal<32>, grid, blk, 0, st, c, nat, internal, inv_scale); break;
+        case 1: hipLaunchKernelGGL(k_to_internal<1>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
+        case 2: hipLaunchKernelGGL(k_to_internal<2>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
+        case 4: hipLaunchKernelGGL(k_to_internal<4>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
+        case 8: hipLaunchKernelGGL(k_to_internal<8>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
+        case 16: hipLaunchKernelGGL(k_to_internal<16>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
+        case 32: hipLaunchKernelGGL(k_to_internal<32>, grid, blk, sm, st, c, nat, internal, inv_scale); break;
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
     XCT_HIP_TRY(hipGetLastError());
@@ -1132,8 +1188,7 @@ int launch_to_internal(const Grid &g, const void *nat, xct_dtype io, int batch, 
 int launch_from_internal64(const Grid &g, const double *internal, int batch, int s0, int F, void *nat, xct_dtype io,
                            hipStream_t st) {
     const ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F64);
-    const int64_t n = g.n_tiles * kTileSlots;
-    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    const dim3 grid((unsigned)((int64_t)g.TH * c.strips)), blk(256);
     switch (F) {
         case 1: hipLaunchKernelGGL(k_from_internal64<1>, grid, blk, 0, st, c, internal, nat); break;
         case 2: hipLaunchKernelGGL(k_from_internal64<2>, grid, blk, 0, st, c, internal, nat); break;
@@ -1149,15 +1204,15 @@ int launch_from_internal(const Grid &g, const float *internal, int batch, int s0
                          hipStream_t st, const float *sub) {
     ConvArgs c = conv_args(g, batch, s0, F, io, XCT_F32);
     c.sub = sub;
-    const int64_t n = g.n_tiles * kTileSlots;
-    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    const dim3 grid((unsigned)((int64_t)g.TH * c.strips)), blk(256);
+    const size_t sm = conv_lds_bytes(F * 4);
     switch (F) {
-        case 1: hipLaunchKernelGGL(k_from_internal<1>, grid, blk, 0, st, c, internal, nat); break;
-        case 2: hipLaunchKernelGGL(k_from_internal<2>, grid, blk, 0, st, c, internal, nat); break;
-        case 4: hipLaunchKernelGGL(k_from_internal<4>, grid, blk, 0, st, c, internal, nat); break;
-        case 8: hipLaunchKernelGGL(k_from_internal<8>, grid, blk, 0, st, c, internal, nat); break;
-        case 16: hipLaunchKernelGGL(k_from_internal<16>, grid, blk, 0, st, c, internal, nat); break;
-        case 32: hipLaunchKernelGGL(k_from_internal<32>, grid, blk, 0, st, c, internal, nat); break;
+        case 1: hipLaunchKernelGGL(k_from_internal<1>, grid, blk, sm, st, c, internal, nat); break;
+        case 2: hipLaunchKernelGGL(k_from_internal<2>, grid, blk, sm, st, c, internal, nat); break;
+        case 4: hipLaunchKernelGGL(k_from_internal<4>, grid, blk, sm, st, c, internal, nat); break;
+        case 8: hipLaunchKernelGGL(k_from_internal<8>, grid, blk, sm, st, c, internal, nat); break;
+        case 16: hipLaunchKernelGGL(k_from_internal<16>, grid, blk, sm, st, c, internal, nat); break;
+        case 32: hipLaunchKernelGGL(k_from_internal<32>, grid, blk, sm, st, c, internal, nat); break;
         default: return fail(XCT_ERR_INVALID, "unsupported fused slice count");
     }
     XCT_HIP_TRY(hipGetLastError());
