@@ -1102,14 +1102,29 @@ __global__ void k_from_internal(ConvArgs c, const float *internal, void *nat) {
     }
 }
 
-// Per-slice max |v| over the natural layout of one fused group.
+// Per-slice max |v| over the natural layout of one fused group (grid.y =
+// slice of the group).  FP32 planes whose length is a multiple of 4 (in a
+// 16-byte aligned array) are read as 16-byte vectors, several per thread.
 __global__ void k_absmax(const void *nat, int io, int64_t plane, int batch, int s0, int F, uint32_t *amax) {
     const int f = blockIdx.y;
     const int s = s0 + f;
     if (s >= batch) return;
     float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(load_io(nat, (int64_t)s * plane + i, io)));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (io == XCT_F32 && (plane & 3) == 0 && ((uintptr_t)nat & 15) == 0) {
+        const f32x4 *p = (const f32x4 *)((const float *)nat + (int64_t)s * plane);
+        const int64_t n4 = plane / 4;
+        auto vmax = [](f32x4 v) { return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))); };
+        int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; i + 3 * stride < n4; i += 4 * stride) {  // four loads in flight
+            const f32x4 v0 = p[i], v1 = p[i + stride], v2 = p[i + 2 * stride], v3 = p[i + 3 * stride];
+            m = fmaxf(m, fmaxf(fmaxf(vmax(v0), vmax(v1)), fmaxf(vmax(v2), vmax(v3))));
+        }
+        for (; i < n4; i += stride) m = fmaxf(m, vmax(p[i]));
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += stride)
+            m = fmaxf(m, fabsf(load_io(nat, (int64_t)s * plane + i, io)));
+    }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     __shared__ float wm[16];
     if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
@@ -1228,9 +1243,11 @@ int launch_pow2_scale(uint32_t *amax, int F, float *scale, float *inv, hipStream
 int launch_natural_scale(const Grid &g, const void *nat, xct_dtype io, int batch, int s0, int F, uint32_t *amax,
                          float *scale, float *inv, hipStream_t st) {
     const int64_t plane = (int64_t)g.H * g.Wd;
-    int blocks = (int)std::min<int64_t>(256, (plane + 1023) / 1024);
+    // 256 threads a workgroup, about 8 vectors (or 32 elements) a thread, at
+    // most 128 workgroups a slice
+    int blocks = (int)std::min<int64_t>(128, (plane + 256 * 32 - 1) / (256 * 32));
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_absmax, dim3(blocks, F), dim3(1024), 0, st, nat, (int)io, plane, batch, s0, F, amax);
+    hipLaunchKernelGGL(k_absmax, dim3(blocks, F), dim3(256), 0, st, nat, (int)io, plane, batch, s0, F, amax);
     XCT_HIP_TRY(hipGetLastError());
     return launch_pow2_scale(amax, F, scale, inv, st);
 }
