@@ -158,6 +158,50 @@ def sq_table(runs, out_md, command, workload, note=""):
         fh.write("\n".join(lines) + "\n")
 
 
+STATE_COUNTERS = ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU",
+                  "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_SCA", "SQ_WAIT_INST_LDS")
+
+
+def _first_two_spmm(csv_path):
+    """Counter values of the first two k_spmm dispatches of a run (A, then A^T)."""
+    vals = defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        if "k_spmm" in r["Kernel_Name"]:
+            vals[int(r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    order = sorted(vals)
+    return vals[order[0]], vals[order[1]]
+
+
+def states_table(runs, out_md, command, workload, note=""):
+    """Markdown table of where the SpMM's wavefronts spend their time: the
+    shares of SQ_WAVE_CYCLES spent waiting on a dependency (SQ_WAIT_ANY),
+    ready but waiting to issue (SQ_WAIT_INST_ANY) and issuing
+    (SQ_ACTIVE_INST_ANY), and the issuing share by instruction kind.  runs:
+    (label, csv of one pass, csv of another pass); each pass holds some of
+    STATE_COUNTERS for the same launches (first A, then A^T)."""
+    lines = [f"# SpMM wavefront states (rocprofv3 --pmc, SQ block): {workload}", "", "Command:", "", "```", command,
+             "```", "", "Shares of the wave cycles (SQ_WAVE_CYCLES) of one launch of A (projection) and one of A^T "
+             "(backprojection); the three states add up to the whole.", "",
+             "| Matrix | Launch | waiting on a dependency | ready, waiting to issue | issuing | of which VALU | LDS | "
+             "vector memory | scalar | waiting to issue an LDS instruction |", "|---" * 10 + "|"]
+    for label, csv_a, csv_b in runs:
+        pa, pb = _first_two_spmm(csv_a), _first_two_spmm(csv_b)
+        for which, i in (("A", 0), ("A^T", 1)):
+            v = dict(pa[i])
+            v.update(pb[i])
+            w = v["SQ_WAVE_CYCLES"]
+            act = v["SQ_ACTIVE_INST_ANY"]
+            lines.append(f"| {label} | {which} | {v['SQ_WAIT_ANY'] / w:.1%} | {v['SQ_WAIT_INST_ANY'] / w:.1%} | "
+                         f"{act / w:.1%} | {v['SQ_ACTIVE_INST_VALU'] / act:.1%} | {v['SQ_ACTIVE_INST_LDS'] / act:.1%} | "
+                         f"{v['SQ_ACTIVE_INST_VMEM'] / act:.1%} | {v['SQ_ACTIVE_INST_SCA'] / act:.1%} | "
+                         f"{v['SQ_WAIT_INST_LDS'] / w:.1%} |")
+    if note:
+        lines += ["", note]
+    lines += ["", f"Kernel sources SHA-256 (code without comments): `{kernel_sources_sha()}`"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_csv")
@@ -166,11 +210,22 @@ def main():
     ap.add_argument("--trace", action="store_true", help="fetch_csv is a kernel_stats.csv, write_csv the output .md")
     ap.add_argument("--sq", action="append", default=[], metavar="LABEL=CSV,BENCH_OUT",
                     help="SQ counter table instead (repeat per matrix dtype); fetch_csv is then the output .md")
+    ap.add_argument("--states", action="append", default=[], metavar="LABEL=CSV,CSV",
+                    help="wavefront-state table instead (two counter passes per matrix dtype); fetch_csv is then the "
+                         "output .md")
     ap.add_argument("--note", default="")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
     a = ap.parse_args()
+    if a.states:
+        runs = []
+        for spec in a.states:
+            label, rest = spec.split("=", 1)
+            csv_a, csv_b = rest.split(",", 1)
+            runs.append((label, csv_a, csv_b))
+        states_table(runs, a.fetch_csv, a.command, a.workload, a.note)
+        return
     if a.sq:
         runs = []
         for spec in a.sq:
