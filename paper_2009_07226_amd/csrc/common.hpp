@@ -149,6 +149,13 @@ struct SpmmLaunch {
     int F;
     xct_dtype vdt;
     int remap;
+    // 16-bit matrices only: write the natural [batch][H][Wd] output of grid *gout
+    // directly (slices s0 .. s0 + F - 1, io dtype, minus sub if set) instead
+    // of the internal rows at yout
+    void *nat = nullptr;
+    const float *sub = nullptr;
+    const Grid *gout = nullptr;
+    int io = 0, batch = 0, s0 = 0;
 };
 int launch_spmm(const SpmmLaunch &L, hipStream_t s);
 // One projection (dir 0) or backprojection (dir 1) of `batch` device slices
