@@ -927,8 +927,7 @@ struct ConvArgs {
 };
 
 // Natural [B][H][Wd] <-> internal [tile][64][F].  One thread per slot: the F
-// loads (or stores) of the natural side are issued together, the internal
-// side is one contiguous row written (or read) with 16-byte accesses.  A
+// loads (or stores) of the natural side are issued together.  A
 // workgroup of 256 threads takes kConvTiles = 4 horizontally adjacent tiles
 // (8 rows x 32 columns), each wavefront two of its rows, so that a natural
 // access of a wavefront is two whole 128-byte row pieces and its internal
