@@ -148,6 +148,36 @@ def test_plan_options_keep_parity(opts):
     assert rel_err(xb.numpy(), oracle.backproject(ATo, yin.double().numpy())).max() <= 1e-5
 
 
+@pytest.mark.parametrize("dt,tol", [("f16", 2e-3), ("bf16", 1.5e-2)])
+@pytest.mark.parametrize("opts", [dict(lane_order=1), dict(tile_waves=32), dict(tile_waves=5, xcd_remap=7),
+                                  dict(fuse=1), dict(fuse=2), dict(fuse=8, lane_order=1), dict(stage_order=1),
+                                  dict(slab_order=1), dict(tile_waves=4, lds_bytes=16384)])
+def test_plan_options_keep_parity_16bit(opts, dt, tol):
+    # 16-bit matrices write their sums straight into the natural output (the
+    # product's epilogue maps each lane's row to its pixel): every lane order,
+    # row tiles per wavefront, block order and fused slice count, with 16-bit
+    # and FP32 io, within the storage-rounding bars
+    N, M, C, B = 64, 90, 64, 5
+    A = gpu_matrix(N, M, C, dt, **opts)
+    Ao, ATo = oracle_mats(N, M, C)
+    x = phantoms.ellipse_batch(N, B, 6, seed=23).float()
+    y_ref = oracle.project(Ao, x.double().numpy().reshape(B, -1))
+    yin = torch.from_numpy(y_ref).float().reshape(B, M, C)  # the oracle's sinogram, as input
+    xb_ref = oracle.backproject(ATo, yin.double().numpy())
+    io16 = torch.float16 if dt == "f16" else torch.bfloat16
+    for io in (torch.float32, io16):
+        y = xct.project(A, x.to(io).cuda())
+        assert y.dtype == io
+        e = rel_err(y.float().cpu().numpy(), y_ref)
+        xb = xct.backproject(A, yin.to(io).cuda())
+        eb = rel_err(xb.float().cpu().numpy(), xb_ref)
+        banner(f"{dt} {opts} io={io}: projection {e.max():.2e} backprojection {eb.max():.2e}")
+        # 16-bit input and output each add their own rounding (at most half
+        # an ulp: 2^-11 relative in FP16, 2^-8 in BF16)
+        bar = tol if io == torch.float32 else tol + 2 * (2.0 ** -11 if dt == "f16" else 2.0 ** -8)
+        assert e.max() <= bar and eb.max() <= bar
+
+
 @pytest.mark.parametrize("dt,kw,expect", [("f32", {}, True), ("f16", {}, True), ("bf16", {}, True),
                                            ("f32", dict(fuse=8), True), ("f32", dict(slab_order=1), False),
                                            ("f32", dict(fuse=4), False), ("f16", dict(fuse=8), False)])
